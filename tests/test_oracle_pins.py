@@ -1,0 +1,505 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these tests re-types the oracle's formula: each checks a closed form
+(vortex-pair motion, thin-aerofoil lift, free fall), an invariant (linear
+impulse, Kelvin's theorem, merge conservation), a special case that reduces
+to a textbook routine (Cramer's rule, LAPACK) or a brute-force evaluation in
+100-digit arithmetic of an algebraically different form of the kernel.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_16079_amd import workloads as W
+
+mpmath.mp.dps = 100
+
+
+def base_params(nb=16, **kw):
+    return W.make_params(nb, **kw)
+
+
+# ------------------------------------------------------------------ P1 kernels
+
+def mp_kernel(dx, dz, rc=None):
+    """(-dz, dx) / (2 pi r^2) or (-dz, dx) / (2 pi sqrt(rc^4 + r^4)) in 100
+    digits -- the simplified algebraic form, not the printed product form."""
+    dx, dz = mpmath.mpf(dx), mpmath.mpf(dz)
+    r2 = dx * dx + dz * dz
+    den = 2 * mpmath.pi * (r2 if rc is None else mpmath.sqrt(mpmath.mpf(rc) ** 4 + r2 * r2))
+    return -dz / den, dx / den
+
+
+def test_p1_kernel_values_against_100_digit_simplified_form():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        dx, dz = rng.normal(size=2) * 10.0 ** rng.uniform(-4, 1)
+        kx, kz = O.kernel_sing(dx, dz)
+        ex, ez = mp_kernel(dx, dz)
+        assert abs(kx - float(ex)) <= 4e-16 * abs(float(ex)) + 1e-300
+        assert abs(kz - float(ez)) <= 4e-16 * abs(float(ez)) + 1e-300
+        kx, kz = O.kernel_reg(dx, dz, 0.01)
+        ex, ez = mp_kernel(dx, dz, 0.01)
+        assert abs(kx - float(ex)) <= 1e-15 * abs(float(ex)) + 1e-300
+        assert abs(kz - float(ez)) <= 1e-15 * abs(float(ez)) + 1e-300
+
+
+def test_p1_kernel_orientation_and_magnitude():
+    # A counter-clockwise (positive) vortex moves a point on its +x side up,
+    # with speed 1/(2 pi r) per unit circulation.
+    kx, kz = O.kernel_sing(0.5, 0.0)
+    assert kx == 0.0 and kz == pytest.approx(1.0 / (2 * math.pi * 0.5), rel=1e-15)
+    kx, kz = O.kernel_sing(0.0, 0.5)
+    assert kx == pytest.approx(-1.0 / (2 * math.pi * 0.5), rel=1e-15) and kz == 0.0
+
+
+def test_p1_regularised_limits():
+    assert O.kernel_reg(0.0, 0.0, 0.01) == (0.0, 0.0)
+    assert O.kernel_sing(0.0, 0.0) == (0.0, 0.0)
+    rc = 0.01
+    for r in (0.05, 0.1, 1.0, 3.0):
+        s = O.kernel_sing(r, 0.0)[1]
+        g = O.kernel_reg(r, 0.0, rc)[1]
+        # K' = K / sqrt(1 + (rc/r)^4): relative gap below (rc/r)^4 / 2
+        assert 0.0 <= (s - g) / s <= 0.5 * (rc / r) ** 4 + 1e-15
+    # inside the core the regularised kernel grows linearly: K' ~ r / (2 pi rc^2)
+    r = 1e-5
+    assert O.kernel_reg(r, 0.0, rc)[1] == pytest.approx(r / (2 * math.pi * rc * rc), rel=1e-9)
+
+
+def test_p1_brute_force_small_systems():
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 3, 4):
+        wx, wz, wg = rng.normal(size=(3, n))
+        nb = rng.integers(0, 4)
+        bx, bz, bg = rng.normal(size=(3, nb))
+        vx, vz = O.wake_velocities(wx, wz, wg, bx, bz, bg, r_core=0.05)
+        for i in range(n):
+            sx = sz = mpmath.mpf(0)
+            for j in range(n):
+                if j != i:
+                    kx, kz = mp_kernel(wx[i] - wx[j], wz[i] - wz[j], 0.05)
+                    sx += kx * wg[j]
+                    sz += kz * wg[j]
+            for j in range(nb):
+                kx, kz = mp_kernel(wx[i] - bx[j], wz[i] - bz[j])
+                sx += kx * bg[j]
+                sz += kz * bg[j]
+            assert abs(vx[i] - float(sx)) <= 1e-14 * (abs(float(sx)) + 1e-3)
+            assert abs(vz[i] - float(sz)) <= 1e-14 * (abs(float(sz)) + 1e-3)
+
+
+# -------------------------------------------------------- P2 / P3 vortex pairs
+
+def test_p2_counter_rotating_pair_translates_at_gamma_over_2pi_d():
+    gam, d, rc, dt, n = 0.4, 0.25, 0.01, 0.005, 200
+    wx = np.array([2.0, 2.0])
+    wz = np.array([0.5 * d, -0.5 * d])
+    wg = np.array([-gam, gam])
+    x0 = wx.copy()
+    for _ in range(n):
+        vx, vz = O.wake_velocities(wx, wz, wg, r_core=rc)
+        wx, wz, wg = O.advect(wx, wz, wg, vx, vz, dt, 0.0)
+    # textbook point-vortex pair speed Gamma/(2 pi d), toward -x; the core
+    # correction d^2/sqrt(rc^4+d^4) is 1 - 1.3e-6 here
+    u_text = gam / (2 * math.pi * d)
+    u_reg = gam * d / (2 * math.pi * math.sqrt(rc ** 4 + d ** 4))
+    disp = wx - x0
+    assert np.allclose(disp, -n * dt * u_reg, rtol=1e-12, atol=0)
+    assert abs(disp[0] / (-n * dt) - u_text) <= 2e-6 * u_text
+    assert wz[0] - wz[1] == pytest.approx(d, abs=1e-15)
+
+
+def test_p3_co_rotating_pair_euler_recurrence():
+    gam, rc, dt = 0.3, 0.02, 0.002
+    wx = np.array([0.1, -0.1])
+    wz = np.array([0.0, 0.0])
+    wg = np.array([gam, gam])
+    R2 = 0.2 ** 2
+    for _ in range(300):
+        vx, vz = O.wake_velocities(wx, wz, wg, r_core=rc)
+        # |K'(R)| = |R| / (2 pi sqrt(rc^4 + |R|^4)); each Euler step adds
+        # (2 Gamma dt |K'|)^2 to |R|^2 because the increment is normal to R
+        kabs = math.sqrt(R2) / (2 * math.pi * math.sqrt(rc ** 4 + R2 ** 2))
+        R2 = R2 + (2 * gam * dt * kabs) ** 2
+        wx, wz, wg = O.advect(wx, wz, wg, vx, vz, dt, 0.0)
+        assert abs(wx[0] + wx[1]) < 1e-15 and abs(wz[0] + wz[1]) < 1e-15  # centroid fixed
+    Rn2 = (wx[0] - wx[1]) ** 2 + (wz[0] - wz[1]) ** 2
+    assert Rn2 == pytest.approx(R2, rel=1e-12)
+
+
+# ----------------------------------------------------------- P4 invariants
+
+def test_p4_impulse_and_circulation_conserved_by_jacobi_euler():
+    rng = np.random.default_rng(3)
+    n, dt = 500, 0.005
+    wx, wz = rng.uniform(0, 3, n), rng.uniform(-0.5, 0.5, n)
+    wg = rng.normal(0, 0.05, n)
+    I0 = np.array([np.sum(wg * wx), np.sum(wg * wz)])
+    G0 = wg.copy()
+    scale = 0.0
+    for _ in range(5):
+        vx, vz = O.wake_velocities(wx, wz, wg, r_core=0.01)
+        scale += dt * np.sum(np.abs(wg) * np.hypot(vx, vz)) + np.sum(np.abs(wg) * np.hypot(wx, wz))
+        wx, wz, wg = O.advect(wx, wz, wg, vx, vz, dt, 0.0)
+    I1 = np.array([np.sum(wg * wx), np.sum(wg * wz)])
+    assert np.array_equal(wg, G0)
+    assert np.max(np.abs(I1 - I0)) <= 1e-13 * scale
+
+
+def test_p4_decay_scales_circulation_geometrically():
+    rng = np.random.default_rng(4)
+    wx, wz, wg = rng.normal(size=(3, 20))
+    g0 = wg.copy()
+    dt, gamma, n = 0.005, 0.1, 50
+    for _ in range(n):
+        vx, vz = O.wake_velocities(wx, wz, wg, r_core=0.01)
+        wx, wz, wg = O.advect(wx, wz, wg, vx, vz, dt, gamma)
+    assert np.allclose(wg, g0 * (1 - gamma * dt) ** n, rtol=1e-13)
+
+
+# ------------------------------------------------------- P5 / P6 surface system
+
+@pytest.mark.parametrize("nb", [16, 32, 64])
+def test_p5_surface_matrix_pose_invariant_and_solve_residual(nb):
+    p = base_params(nb)
+    rng = np.random.default_rng(nb)
+    g1 = np.array([0.3, -0.2, 0.4, 0.1, 5.0, 0.3, 1.0])
+    g2 = np.array([-1.7, 2.2, -1.1, 0.0, 1.0, 0.0, -3.0])
+    a1, a2 = O.surface_matrix(p, g1), O.surface_matrix(p, g2)
+    # world coordinates of size ~3 m against a half-panel of c / (2 N_b) lose
+    # ~ 2 eps * 3 / (c / 2 N_b) relative per entry
+    tol = 4 * 2.2e-16 * 3.0 / (0.5 * p["chord"] / nb)
+    assert np.max(np.abs(a1 - a2)) <= tol * np.max(np.abs(a1))
+    b = rng.normal(size=nb + 2)
+    x = O.solve(a1, b)
+    assert np.linalg.norm(a1 @ x - b) <= 1e-12 * np.linalg.norm(b)
+    assert np.allclose(x, np.linalg.solve(a1, b), rtol=1e-10, atol=1e-12 * np.abs(x).max())
+    assert np.linalg.cond(a1) < 1e6
+
+
+def test_p5_one_bound_vortex_matches_cramers_rule():
+    p = base_params(1)
+    a = O.surface_matrix(p, np.zeros(7))
+    assert a.shape == (3, 3)
+    b = np.array([0.3, -0.7, 0.2])
+    det = np.linalg.det
+
+    def cramer(a, b):
+        d = (a[0, 0] * (a[1, 1] * a[2, 2] - a[1, 2] * a[2, 1])
+             - a[0, 1] * (a[1, 0] * a[2, 2] - a[1, 2] * a[2, 0])
+             + a[0, 2] * (a[1, 0] * a[2, 1] - a[1, 1] * a[2, 0]))
+        out = []
+        for c in range(3):
+            m = a.copy()
+            m[:, c] = b
+            out.append((m[0, 0] * (m[1, 1] * m[2, 2] - m[1, 2] * m[2, 1])
+                        - m[0, 1] * (m[1, 0] * m[2, 2] - m[1, 2] * m[2, 0])
+                        + m[0, 2] * (m[1, 0] * m[2, 1] - m[1, 1] * m[2, 0])) / d)
+        return np.array(out)
+    assert abs(det(a)) > 0
+    assert np.allclose(O.solve(a, b), cramer(a, b), rtol=1e-12)
+
+
+def test_p5_elimination_matches_lapack_on_random_systems():
+    rng = np.random.default_rng(9)
+    for n in (3, 10, 34, 66):
+        a = rng.normal(size=(n, n))
+        b = rng.normal(size=n)
+        assert np.allclose(O.solve(a, b), np.linalg.solve(a, b), rtol=1e-9, atol=1e-11)
+
+
+def test_p6_plate_at_zero_incidence_carries_no_circulation():
+    p = base_params(16)
+    nc = 17
+    # plate moving along its chord (theta = 0, velocity (U, 0)) in still air
+    gs, rc = O.plate_solve_pose(p, [0, 0, 0, 6.0, 0.0, 0.0], np.zeros((nc, 2)), 0.0)
+    assert rc == 0
+    assert np.max(np.abs(gs)) < 1e-14
+
+
+def test_p6_kelvin_total_circulation_stays_zero():
+    wl = W.plain_single_plan(K=2, H=40)
+    p = dict(wl.params, decay=0.0, n_wake_max=0)
+    out = O.rollout_batch(p, wl.K, wl.H, wl.dt, wl.g0, wl.gb0, wl.field_off,
+                          wl.field_of, wl.wx, wl.wz, wl.wg, wl.pairs, wl.u, wl.x_goal,
+                          wl.q_diag, gamma_s=True)
+    gs = out["gamma_s"]           # [K, H, S]
+    nb = p["n_bound"]
+    w0 = wl.wg.sum()
+    for k in range(wl.K):
+        shed_total = 0.0
+        for n in range(wl.H):
+            wake_total = w0 + shed_total
+            assert abs(gs[k, n].sum() + wake_total) < 1e-12
+            shed_total += gs[k, n, nb] + gs[k, n, nb + 1]
+
+
+# --------------------------------------------------- P7 / P8 / P10 thin plate
+
+def thin_plate_run(alpha_deg, nb=16, steps=400):
+    U, dt = 6.0, 0.005
+    a = math.radians(alpha_deg)
+    p = base_params(nb, decay=0.0, n_wake_max=0, shed_mode=W.SHED_TE, prescribed=1,
+                    r_core=0.01)
+    g0 = np.array([[0.0, 0.0, a, 0.0, U, 0.0, 0.0]])
+    out = O.rollout_batch(p, 1, steps, dt, g0, np.zeros((1, nb)),
+                          np.array([0, 0], dtype=np.int64), None, np.zeros(0), np.zeros(0),
+                          np.zeros(0), None, np.zeros((1, steps)), W.X_GOAL, W.Q_POS_PITCH,
+                          force=True)
+    f = out["force"][0]           # (F_x, F_z, M_w) per step
+    q = 0.5 * p["rho"] * U * U * p["chord"] * p["span"]
+    return p, a, f, q
+
+
+def test_p7_thin_plate_lift_reaches_2pi_sin_cos2():
+    p, a, f, q = thin_plate_run(2.0)
+    cl = f[:, 1] / q
+    steady = 2 * math.pi * math.sin(a) * math.cos(a) ** 2
+    # 400 steps is s = 2 U t / c = 80 semichords: Wagner's function is 0.996
+    assert cl[-1] == pytest.approx(steady, rel=0.03)
+    # lift builds up from the impulsive start (Wagner): early below late
+    assert cl[50] < cl[-1]
+    # drag-direction force is the normal force's x part: F_x / F_z = -tan(alpha)
+    assert f[-1, 0] / f[-1, 1] == pytest.approx(-math.tan(a), rel=1e-9)
+
+
+def test_p8_centre_of_pressure_near_quarter_chord():
+    p, a, f, q = thin_plate_run(2.0, nb=16)
+    fn = math.hypot(f[-1, 0], f[-1, 1])
+    c, nb = p["chord"], p["n_bound"]
+    arm = f[-1, 2] / fn
+    assert arm == pytest.approx(0.25 * c * (1 - 1.0 / nb), rel=0.05)
+
+
+def test_p10_lift_up_and_nose_up_moment_for_positive_incidence():
+    _, _, f, _ = thin_plate_run(4.0, nb=8, steps=100)
+    assert f[-1, 1] > 0 and f[-1, 2] > 0
+    _, _, f, _ = thin_plate_run(-4.0, nb=8, steps=100)
+    assert f[-1, 1] < 0 and f[-1, 2] < 0
+
+
+# ------------------------------------------------------ P9 rotation reading
+
+def test_p9_pitching_plate_sees_relative_normal_flow():
+    p = base_params(16)
+    nb, c, om = 16, p["chord"], 2.0
+    gs, rc = O.plate_solve_pose(p, [0, 0, 0, 0, 0, om], np.zeros((nb + 1, 2)), 0.0)
+    a = O.surface_matrix(p, np.zeros(7))
+    s = np.arange(nb + 1) * c / nb          # arclength of collocation points from LE
+    # a point a distance (c/2 - s) ahead of the pivot moves along +n at om (c/2 - s);
+    # no-through-flow needs the bound system to cancel that relative inflow
+    b_expected = np.concatenate([-om * (s - 0.5 * c), [0.0]])
+    assert np.allclose(a @ gs, b_expected, atol=1e-12)
+
+
+# ----------------------------------------------------- P11 glider dynamics
+
+def test_p11_free_fall_without_air():
+    wl = W.plain_single_plan(K=1, H=60)
+    p = dict(wl.params, rho=0.0)
+    g0 = np.array([[0.0, 1.0, 0.0, 0.0, 6.0, 0.5, 0.0]])
+    out = O.rollout_batch(p, 1, wl.H, wl.dt, g0, wl.gb0, wl.field_off, wl.field_of,
+                          wl.wx, wl.wz, wl.wg, wl.pairs, np.zeros((1, wl.H)), wl.x_goal,
+                          wl.q_diag, traj=True)
+    tr = out["traj"][0]
+    n = np.arange(wl.H + 1)
+    dt, gg = wl.dt, p["grav"]
+    assert np.allclose(tr[:, 1], 1.0 + n * dt * 0.5 - gg * dt * dt * n * (n - 1) / 2, atol=1e-12)
+    assert np.allclose(tr[:, 0], n * dt * 6.0, atol=1e-12)
+    assert np.allclose(tr[:, 2], 0.0) and np.allclose(tr[:, 6], 0.0)
+
+
+def test_p11_elevator_moment_identity_and_zero_incidence():
+    p = base_params(16)
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        g = np.concatenate([rng.normal(size=2), rng.uniform(-1, 1, 2), rng.normal(size=3) + [5, 0, 0]])
+        alpha, xe, fe = O.elevator(p, g, rng.normal())
+        arm = xe - g[:2]
+        moment = arm[0] * fe[1] - arm[1] * fe[0]
+        th, ph = g[2], g[3]
+        ne = np.array([-math.sin(th + ph), math.cos(th + ph)])
+        f_mag = fe @ ne
+        assert np.allclose(fe, f_mag * ne, atol=1e-15)
+        assert moment == pytest.approx(-(p["l_body"] * math.cos(ph) + p["l_elev"]) * f_mag,
+                                       rel=1e-12, abs=1e-15)
+    alpha, _, fe = O.elevator(p, [0, 0, 0, 0, 6.0, 0, 0], 0.0)
+    assert alpha == 0.0 and np.all(fe == 0.0)
+    # deflected elevator in level flight: C_n = 2 sin(phi), normal force up-ish
+    ph = 0.1
+    alpha, _, fe = O.elevator(p, [0, 0, 0, ph, 6.0, 0, 0], 0.0)
+    assert alpha == pytest.approx(ph, rel=1e-14)
+    assert math.hypot(*fe) == pytest.approx(p["rho"] * 36.0 * p["s_elev"] * math.sin(ph), rel=1e-12)
+
+
+# ------------------------------------------------------------- P12 merging
+
+def test_p12_merge_conserves_circulation_and_uses_mean_position():
+    p = base_params(8, decay=0.0, n_wake_max=4)
+    wx = np.array([1.0, 1.2, 1.5])
+    wz = np.array([0.3, -0.2, 0.1])
+    wg = np.array([0.05, -0.02, 0.03])
+    g0 = np.array([[0.0, 0.0, 0.05, 0.0, 6.0, 0.0, 0.0]])
+    out = O.rollout_batch(p, 1, 1, 0.005, g0, np.zeros((1, 8)),
+                          np.array([0, 3], dtype=np.int64), None, wx, wz, wg, None,
+                          np.zeros((1, 1)), W.X_GOAL, W.Q_POS_PITCH, final_wake=True,
+                          vel_last=True, gamma_s=True)
+    assert out["n_final"][0] == 4 and out["n_vel_last"][0] == 5
+    v = out["vel_last"]
+    adv_x = wx + 0.005 * v[:3, 0]
+    adv_z = wz + 0.005 * v[:3, 1]
+    assert out["wx"][0] == pytest.approx(0.5 * (adv_x[0] + adv_x[1]), abs=1e-15)
+    assert out["wz"][0] == pytest.approx(0.5 * (adv_z[0] + adv_z[1]), abs=1e-15)
+    assert out["wg"][0] == wg[0] + wg[1]
+    assert out["wx"][1] == pytest.approx(adv_x[2], abs=1e-15)
+    gs = out["gamma_s"][0, 0]
+    total = out["wg"][:4].sum()
+    assert total == pytest.approx(wg.sum() + gs[8] + gs[9], abs=1e-16)
+
+
+def test_p12_wake_never_exceeds_cap():
+    wl = W.plain_single_plan(K=2, H=30)
+    p = dict(wl.params, n_wake_max=25)
+    out = O.rollout_batch(p, wl.K, wl.H, wl.dt, wl.g0, wl.gb0, wl.field_off,
+                          wl.field_of, wl.wx, wl.wz, wl.wg, wl.pairs, wl.u, wl.x_goal, wl.q_diag,
+                          final_wake=True)
+    assert np.all(out["n_final"] == 25)
+
+
+# --------------------------------------------------------- P13 termination
+
+def test_p13_termination_geometry():
+    p = base_params(16)
+    g = np.zeros(7)          # wing mid-chord at (-l_w, 0), chord along x, normal +z
+    geo = O.plate_geometry(p, g)
+    le, te = geo["rc"][0], geo["rc"][-1]
+    mid = 0.5 * (le + te)
+    h = 0.02 * p["chord"]
+    hit = lambda a, b: O.segment_hits_plate(p, g, np.array(a), np.array(b))
+    assert hit(mid + [0, 0.1], mid + [0, -0.1])              # straddles the chord
+    assert not hit(mid + [0, 0.1], mid + [0, 0.2])           # entirely above
+    assert hit(mid + [0, -0.5 * h], mid + [0.01, -0.5 * h])  # inside the inflated band
+    assert not hit(mid + [0, -2 * h], mid + [0, -3 * h])     # below the band
+    assert hit(mid + [0, 0.1], mid + [0, 0.0])               # touches the chord (closed)
+    assert hit(le + [0, 0.1], le + [0, -0.1])                # through the LE point
+    assert not hit(le + [0.01, 0.1], le + [0.01, -0.1])      # ahead of the LE
+    assert not hit(te + [-0.01, 0.1], te + [-0.01, -0.1])    # behind the TE
+
+
+def test_p13_rollout_zeroes_a_pair_that_crosses_the_wing():
+    p = base_params(16, decay=0.0)
+    g0 = np.zeros((1, 7))
+    g0[0, 4] = 6.0
+    geo = O.plate_geometry(p, g0[0])
+    mid = 0.5 * (geo["rc"][0] + geo["rc"][-1])
+    wx = np.array([mid[0], mid[0], 1.0])
+    wz = np.array([0.1, -0.1, 0.5])
+    wg = np.array([-0.2, 0.2, 0.01])
+    out = O.rollout_batch(p, 1, 1, 0.005, g0, np.zeros((1, 16)),
+                          np.array([0, 3], dtype=np.int64), None, wx, wz, wg,
+                          np.array([[0, 1]], dtype=np.int32), np.zeros((1, 1)), W.X_GOAL,
+                          W.Q_POS_PITCH, final_wake=True)
+    assert out["wg"][0] == 0.0 and out["wg"][1] == 0.0 and out["wg"][2] == 0.01
+
+
+# ------------------------------------------------------------ P14 softmin
+
+def test_p14_softmin_identities():
+    rng = np.random.default_rng(1)
+    K, H = 50, 7
+    J = rng.uniform(1, 5, K)
+    mu = rng.normal(size=H)
+    eps = rng.normal(size=(K, H))
+    r = O.mppi(J, 1.0, mu, mu + eps)
+    assert r["w"].sum() == pytest.approx(1.0, abs=1e-14)
+    assert r["argmin"] == int(np.argmin(J)) and np.argmax(r["w"]) == r["argmin"]
+    r0 = O.mppi(J, 1e-6, mu, mu + eps)
+    assert r0["w"][r0["argmin"]] == pytest.approx(1.0) and np.allclose(r0["xi_star"], (mu + eps)[r0["argmin"]])
+    rinf = O.mppi(J, 1e12, mu, mu + eps)
+    assert np.allclose(rinf["w"], 1.0 / K) and np.allclose(rinf["xi_star"], mu + eps.mean(0))
+    rz = O.mppi(J, 1.0, mu, np.tile(mu, (K, 1)))
+    assert np.allclose(rz["xi_star"], mu, atol=1e-15)
+    # brute force for K = 3: weights e^{-(J - Jmin)} / sum
+    J3 = np.array([2.0, 1.0, 3.0])
+    xi3 = np.array([[1.0], [2.0], [4.0]])
+    r3 = O.mppi(J3, 1.0, np.zeros(1), xi3)
+    e = [math.exp(-1.0), 1.0, math.exp(-2.0)]
+    s = sum(e)
+    assert np.allclose(r3["w"], np.array(e) / s, rtol=1e-15)
+    assert r3["xi_star"][0] == pytest.approx((e[0] * 1 + e[1] * 2 + e[2] * 4) / s, rel=1e-15)
+
+
+def test_p14_ties_and_nonfinite_costs():
+    J = np.array([3.0, 1.0, 1.0, np.inf, np.nan])
+    r = O.mppi(J, 1.0, np.zeros(2), np.ones((5, 2)))
+    assert r["argmin"] == 1 and r["w"][3] == 0.0 and r["w"][4] == 0.0
+    assert r["w"][1] == r["w"][2]
+    r = O.mppi(np.array([np.inf, np.nan]), 1.0, np.array([0.5, -0.5]), np.ones((2, 2)))
+    assert r["argmin"] == -1 and np.all(r["w"] == 0) and np.array_equal(r["xi_star"], [0.5, -0.5])
+
+
+# ------------------------------------------- P16 unsteady loads (readings R13)
+
+def _prescribed(nb, mode, g0, steps, dt=0.005, **kw):
+    p = base_params(nb, decay=0.0, n_wake_max=0, shed_mode=mode, prescribed=1, **kw)
+    out = O.rollout_batch(p, 1, steps, dt, np.array([g0]), np.zeros((1, nb)),
+                          np.array([0, 0], dtype=np.int64), None, np.zeros(0), np.zeros(0),
+                          np.zeros(0), None, np.zeros((1, steps)), W.X_GOAL, W.Q_POS_PITCH,
+                          force=True, gamma_s=True, traj=True, final_wake=True)
+    return p, out
+
+
+@pytest.mark.parametrize("nb", [16, 64, 256])
+def test_p16_impulsive_plunge_gives_flat_plate_added_mass(nb):
+    # A plate set impulsively into plunge at w (no shedding, no circulation)
+    # feels the potential-flow added-mass force -rho pi (c/2)^2 s w / dt on the
+    # first step; the discrete plate converges to it as N_b grows.
+    w, dt = 0.5, 0.005
+    p, out = _prescribed(nb, W.SHED_NONE, [0, 0, 0, 0, 0, w, 0], 2, dt)
+    ma = p["rho"] * math.pi * (0.5 * p["chord"]) ** 2 * p["span"]
+    ratio = out["force"][0, 0, 1] / (-ma * w / dt)
+    assert abs(ratio - 1.0) <= 1.0 / nb + 1e-9
+    assert np.all(out["force"][0, 1, :2] == 0.0)   # steady plunge: no force after
+
+
+def _impulse(p, nb, mode, out_prev, out_now, n):
+    """rho s sum Gamma (z, -x) over bound, wake and shed vortices after the
+    solve of step n (wake positions from the run that stopped before step n)."""
+    nw = out_prev["n_final"][0]
+    geo = O.plate_geometry(p, out_now["traj"][0, n])
+    gs = out_now["gamma_s"][0, n]
+    G = list(out_prev["wg"][:nw]) + list(gs[:nb])
+    X = list(out_prev["wx"][:nw]) + list(geo["rb"][:, 0])
+    Z = list(out_prev["wz"][:nw]) + list(geo["rb"][:, 1])
+    shed = [(gs[nb], geo["r_lev"]), (gs[nb + 1], geo["r_tev"])] if mode == W.SHED_BOTH else \
+        [(gs[nb], geo["r_tev"])]
+    for gam, r in shed:
+        G.append(gam)
+        X.append(r[0])
+        Z.append(r[1])
+    G, X, Z = map(np.asarray, (G, X, Z))
+    return p["rho"] * p["span"] * np.array([np.sum(G * Z), -np.sum(G * X)])
+
+
+@pytest.mark.parametrize("mode", [W.SHED_TE, W.SHED_BOTH])
+def test_p16_bernoulli_lift_agrees_with_vortex_impulse_theorem(mode):
+    # The force on a body in unbounded 2D flow is minus the rate of change of
+    # the vortex impulse rho sum Gamma (z, -x) of all (bound + free) vorticity.
+    nb, N, a = 16, 60, math.radians(5.0)
+    g0 = [0.0, 0.0, a, 0.0, 6.0, 0.0, 0.0]
+    runs = [_prescribed(nb, mode, g0, H)[1] for H in (N - 1, N, N + 1)]
+    p = base_params(nb)
+    I1 = _impulse(p, nb, mode, runs[0], runs[1], N - 1)
+    I2 = _impulse(p, nb, mode, runs[1], runs[2], N)
+    f_imp = -(I2 - I1) / 0.005
+    f_bern = runs[1]["force"][0, N - 1]
+    assert f_bern[1] > 0 and f_imp[1] > 0
+    if mode == W.SHED_TE:
+        assert f_bern[1] == pytest.approx(f_imp[1], rel=0.02)
+    else:
+        # both edges shed: same sign and magnitude within a factor of two
+        assert 0.5 < f_bern[1] / f_imp[1] < 2.0
