@@ -1,0 +1,200 @@
+/*
+ * vpm.h -- C ABI of the MI355X (gfx950) rollout engine for the vortex
+ * particle glider planner of Gupta, Wolfe, Perrotta and Moore, "Real-Time
+ * Maneuver Planning for Fixed-Wing UAVs in Unsteady Flows Using a
+ * GPU-Accelerated Vortex Particle Model" (arXiv 2509.16079).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status (VPM_OK = 0, VPM_PENDING = 1 from
+ *    planner_poll only, negative on error) and never throws. On error,
+ *    vpm_last_error() returns a message for the calling thread.
+ *  - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors
+ *    on the context's device) unless marked "host". The caller owns them; the
+ *    library only reads inputs and only writes outputs.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream: inputs must stay alive and
+ *    outputs must not be read until the stream has been synchronised.
+ *  - Floating-point arrays are double in memory whatever the compute
+ *    precision; VPM_FP32C computes the interaction sums in FP32 with
+ *    compensated per-target accumulation and keeps the surface solve and the
+ *    circulation sums in FP64.
+ *  - Coordinates: x forward, z up, angles counter-clockwise (nose up), and a
+ *    positive circulation turns counter-clockwise.
+ */
+#ifndef VPM_H
+#define VPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VPM_API __attribute__((visibility("default")))
+
+/* ---------------------------------------------------------- status codes */
+#define VPM_OK 0
+#define VPM_PENDING 1     /* planner_poll: the request has not finished      */
+#define VPM_EINVAL (-1)   /* bad argument                                    */
+#define VPM_ENOMEM (-2)   /* device or host allocation failed                */
+#define VPM_EDEVICE (-3)  /* HIP error (no device, launch failure, ...)      */
+#define VPM_ESINGULAR (-4) /* the plate system has a zero pivot              */
+#define VPM_EBUDGET (-5)  /* a planner request exceeds the HBM budget alone  */
+#define VPM_ECAPACITY (-6) /* a wake does not fit the kernel's limits         */
+#define VPM_ENOTFOUND (-7) /* unknown planner ticket or state                */
+
+/* per-rollout status bits written by vpm_rollout_batch */
+#define VPM_ROLLOUT_NONFINITE 1 /* a final glider value is NaN or infinite  */
+#define VPM_ROLLOUT_CAPACITY 2  /* the initial wake exceeds max_wake0       */
+#define VPM_ROLLOUT_BADFIELD 4  /* field_of[k] outside 0..n_fields-1, or its
+                                   offsets decrease                          */
+
+/* shedding modes: which edge vortices are unknowns of the surface system */
+#define VPM_SHED_BOTH 0 /* an LEV and a TEV every step (Sec. III-A)          */
+#define VPM_SHED_TE 1   /* TEV only (Kutta condition at the trailing edge)    */
+#define VPM_SHED_NONE 2 /* no shedding                                        */
+
+/* compute precision */
+#define VPM_FP32C 0 /* FP32 interactions, compensated sums; FP64 solve        */
+#define VPM_FP64 1  /* FP64 throughout                                        */
+
+/* Model parameters (Sec. III-A and III-B), copied at each call. */
+typedef struct {
+  int32_t n_bound;    /* N_b bound vortices on the chord, 1..64            */
+  int32_t n_wake_max; /* N_w,max: merge the two oldest above it; <= 0: off */
+  int32_t shed_mode;  /* VPM_SHED_*; vpm_rollout_batch takes BOTH only     */
+  int32_t precision;  /* VPM_FP32C or VPM_FP64                             */
+  double chord;       /* c [m]                                             */
+  double shed_frac;   /* delta_s / c; the paper uses 0.02                  */
+  double r_core;      /* core radius of the regularised kernel [m], > 0    */
+  double decay;       /* gamma of dGamma_w/dt = -gamma Gamma_w [1/s]        */
+  double rho;         /* air density [kg/m^3]                              */
+  double span;        /* wing span s [m]                                   */
+  double grav;        /* g [m/s^2]                                         */
+  double mass;        /* m [kg], > 0                                       */
+  double inertia;     /* I [kg m^2], > 0                                   */
+  double l_body;      /* l: CG to elevator hinge [m]                       */
+  double l_wing;      /* l_w: CG to wing mid-chord [m]                     */
+  double l_elev;      /* l_e: elevator length [m]                          */
+  double s_elev;      /* S_e: elevator area [m^2]                          */
+} vpm_params;
+
+/* One batch of K independent rollouts of H explicit-Euler steps of the
+ * coupled VPM-glider model (Sec. III-A, III-B). Wake fields are stored once
+ * and shared: rollout k starts from field fo = field_of[k] (field_of NULL:
+ * fo = k), the entries [field_off[fo], field_off[fo+1]) of wx/wz/wg in age
+ * order (oldest first). */
+typedef struct {
+  int32_t K;              /* rollouts, >= 1                                 */
+  int32_t H;              /* steps per rollout, >= 1                        */
+  double dt;              /* step [s], > 0                                  */
+  int32_t n_fields;       /* number of wake fields, >= 1                    */
+  int32_t max_wake0;      /* upper bound of every field's size; a rollout
+                             whose field is larger gets VPM_ROLLOUT_CAPACITY */
+  int32_t n_pairs;        /* disturbance pairs per rollout, 0..4            */
+  int32_t reserved;
+  const double *g0;       /* [K][7] glider state (x, z, th, phi, xd, zd, thd) */
+  const double *gb0;      /* [K][N_b] previous-step bound circulations       */
+  const int64_t *field_off; /* [n_fields + 1] nondecreasing, field_off[0]=0 */
+  const int32_t *field_of;  /* [K] field index per rollout, or NULL         */
+  const double *wx;       /* [field_off[n_fields]] wake x [m]               */
+  const double *wz;       /* wake z [m]                                     */
+  const double *wg;       /* wake circulation [m^2/s]                       */
+  const int32_t *pairs;   /* [K][2 n_pairs] field indices of the two vortices
+                             of each disturbance pair (Sec. V), -1 = none;
+                             NULL when n_pairs = 0                          */
+  const double *u_mean;   /* [H] mean elevator rate (control u = phi_dot)   */
+  const double *u_eps;    /* [K][H] perturbation of rollout k; the control of
+                             step n is u_mean[n] + u_eps[k][n]              */
+  double x_goal[7];       /* host values: goal state of the cost (Eq. 24)   */
+  double q_diag[7];       /* host values: diagonal of Q (Eq. 24)            */
+} vpm_batch_in;
+
+/* Outputs of vpm_rollout_batch. Required: g_final, cost, status. Optional
+ * (NULL to skip): traj, gamma_s, pair_count, and the wake block. The wake
+ * block (all of wake_off, n_final and at least one of wx/wz/wg/vel_last)
+ * uses per-rollout capacity wake_off[k+1] - wake_off[k], which must be at
+ * least N_0 + 2H; entries beyond the count are left untouched. */
+typedef struct {
+  double *g_final;        /* [K][7] state after H steps                     */
+  double *cost;           /* [K] J of Eq. 24; +inf when non-finite          */
+  int32_t *status;        /* [K] VPM_ROLLOUT_* bits                         */
+  double *traj;           /* [K][H+1][7] states, or NULL                    */
+  double *gamma_s;        /* [K][H][N_b+2] surface circulations per step
+                             (bound, LEV, TEV), or NULL                     */
+  int64_t *pair_count;    /* [K] pair-interactions the rollout's steps
+                             comprise (method count), or NULL               */
+  const int64_t *wake_off; /* [K+1] output capacity layout, or NULL         */
+  double *wx;             /* final wake x (after merging), or NULL          */
+  double *wz;             /* final wake z, or NULL                          */
+  double *wg;             /* final wake circulation, or NULL                */
+  int32_t *n_final;       /* [K] final wake count                           */
+  double *vel_last;       /* [wake_off[K]][2] velocity of each vortex
+                             advected in the last step (FIFO order, before
+                             merging), or NULL                              */
+  int32_t *n_vel_last;    /* [K] count of vel_last entries, or NULL         */
+} vpm_batch_out;
+
+typedef struct vpm_ctx vpm_ctx;
+
+/* Create a context on HIP device `device` (an index as hipSetDevice takes).
+ * The context caches the FP64 plate-system inverses and the kernel tuning
+ * table. Returns VPM_EDEVICE if the device is absent or is not gfx950. */
+VPM_API int vpm_create(vpm_ctx **out, int device);
+VPM_API void vpm_destroy(vpm_ctx *ctx);
+
+/* Message of the calling thread's last error ("" if none). */
+VPM_API const char *vpm_last_error(void);
+
+/* Host-only argument check of vpm_rollout_batch (no HIP call): returns
+ * VPM_OK or the error vpm_rollout_batch would return for these arguments. */
+VPM_API int vpm_validate_batch(const vpm_params *params, const vpm_batch_in *in,
+                               const vpm_batch_out *out);
+
+/* Batched rollouts (Sec. III-A/B stepping, Eq. 24 cost). Each step: surface
+ * velocities (Eq. 12), the surface solve K Gamma_S = b (Eqs. 8-11) with the
+ * Kelvin row, unsteady Bernoulli loads (Eqs. 13-15), elevator force and
+ * rigid-body accelerations (Sec. III-B), LEV/TEV shedding, wake velocities
+ * (Eq. 16) over the wake and the bound vortices, explicit Euler advection
+ * and decay (Eq. 17), merging of the two oldest vortices above N_w,max, the
+ * disturbance termination test (Sec. V) and the explicit Euler glider step.
+ * Errors: VPM_EINVAL (bad sizes, NULL required pointers, shed_mode other
+ * than BOTH), VPM_ECAPACITY (max_wake0 + 2H beyond the kernel's LDS limit),
+ * VPM_ESINGULAR, VPM_EDEVICE. */
+VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
+                              const vpm_batch_in *in, vpm_batch_out *out,
+                              void *stream);
+
+/* Standalone batched FP64 surface solve (Eqs. 10-12): for B wing poses
+ * pose[b] = (x_w, z_w, th, xd_w, zd_w, thd) with wake-induced velocities
+ * vw_c[b][i] (i = 0..N_b, collocation points from LE to TE) and wake
+ * circulation sums sum_gw[b], writes the surface circulations gamma_s[b][S]
+ * (S = N_b + 2 / N_b + 1 / N_b for BOTH / TE / NONE: bound first, then LEV,
+ * then TEV). Errors: VPM_EINVAL, VPM_ESINGULAR, VPM_EDEVICE. */
+VPM_API int vpm_plate_solve(vpm_ctx *ctx, const vpm_params *params, int32_t B,
+                            const double *pose, const double *vw_c,
+                            const double *sum_gw, int32_t shed_mode,
+                            double *gamma_s, void *stream);
+
+/* MPPI reweighting (Eq. 25). cost[K]; weights w_out[i] = exp(-(J_i -
+ * J_min)/lambda) / sum_j exp(-(J_j - J_min)/lambda) (non-finite costs get
+ * 0); u_new[h] = u_mean[h] + sum_i w_i u_eps[i][h]; *argmin (device int32,
+ * lowest index on ties) and *jmin (device double). With no finite cost:
+ * weights 0, u_new = u_mean, argmin = -1, jmin = +inf. Errors: VPM_EINVAL
+ * (K < 1, H < 1, lambda <= 0, NULL pointers), VPM_EDEVICE. */
+VPM_API int mppi_weights(vpm_ctx *ctx, int32_t K, int32_t H, const double *cost,
+                         double lambda, const double *u_mean,
+                         const double *u_eps, double *w_out, double *u_new,
+                         int32_t *argmin, double *jmin, void *stream);
+
+/* Exact pair-interaction count of one rollout (host arithmetic): per step
+ * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b
+ * bound pairs with N_w' = N_w + 2, merging above n_wake_max (> 0). */
+VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,
+                               int32_t n_wake_max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPM_H */

@@ -19,6 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "vpm_oracle.c")
 LIB = os.path.join(HERE, "libvpm_oracle.so")
+LIB_F32 = os.path.join(HERE, "libvpm_oracle_f32state.so")
 
 SHED_BOTH, SHED_TE, SHED_NONE = 0, 1, 2
 OK, NONFINITE, CAPACITY, SINGULAR = 0, 1, 2, 4
@@ -46,25 +47,32 @@ class Params(C.Structure):
     ]
 
 
+def _stale(path):
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, no fast-math, no contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
-               "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", SRC, "-o", LIB + ".tmp", "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(LIB + ".tmp", LIB)
+    """Compile the oracle with gcc (plain C11, no fast-math, no contraction),
+    and its binary32-state variant."""
+    for path, extra in ((LIB, []), (LIB_F32, ["-DORC_F32_STATE"])):
+        if force or _stale(path):
+            cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
+                   "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"] + extra + \
+                  [SRC, "-o", path + ".tmp", "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(path + ".tmp", path)
     return LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+def lib(f32_state: bool = False):
+    path = LIB_F32 if f32_state else LIB
+    if path not in _libs:
+        if _stale(path):
             build(force=True)
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         d, i32, P = C.c_double, C.c_int32, C.c_void_p
         L.orc_kernel_sing.argtypes = [d, d, P, P]
         L.orc_kernel_reg.argtypes = [d, d, d, P, P]
@@ -88,8 +96,8 @@ def lib():
         L.orc_cost.argtypes = [P, P, P]
         L.orc_cost.restype = d
         L.orc_mppi.argtypes = [i32, i32, P, d, P, P, P, P, P, P]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _p(a):
@@ -213,12 +221,13 @@ def mppi(cost_arr, lam, mu, xi):
 def rollout_batch(params: dict, K, H, dt, g0, gb0, field_off, field_of, wx, wz, wg,
                   pairs, u, x_goal, q_diag, *, traj=False, gamma_s=False, force=False,
                   final_wake=False, vel_last=False, reverse=False, n_threads=0,
-                  rollouts=None):
+                  rollouts=None, f32_state=False):
     """Run the oracle on rollouts ``rollouts`` (default: all K) of a batch.
 
     Inputs follow the layout of ``orc_rollout_batch``; ``u`` is the full
     control (mean + perturbation), shape [K, H]. Returns a dict of numpy
-    arrays indexed by position in ``rollouts``.
+    arrays indexed by position in ``rollouts``. ``f32_state`` runs the
+    binary32-storage variant.
     """
     p = make_params(params)
     nb = params["n_bound"]
@@ -255,7 +264,7 @@ def rollout_batch(params: dict, K, H, dt, g0, gb0, field_off, field_of, wx, wz, 
             out["vel_last"] = np.zeros((tot, 2))
             out["n_vel_last"] = np.zeros(k, dtype=np.int32)
         out["out_off"] = out_off
-    lib().orc_rollout_batch(
+    lib(f32_state).orc_rollout_batch(
         C.byref(p), k, H, float(dt), _p(g0), _p(gb0), _p(field_off), _p(fo),
         _p(wx), _p(wz), _p(wg), _p(pr), n_pairs, _p(u), _p(_f64(x_goal)), _p(_f64(q_diag)),
         int(reverse), int(n_threads), _p(out["g_final"]), _p(out["cost"]), _p(out["status"]),

@@ -16,6 +16,12 @@
  *   Sec. V      disturbance pair and its termination at the wing
  * Readings where the paper is silent or garbled are marked READING and are
  * listed, with the pins that ground them, in the design notes.
+ *
+ * Built with -DORC_F32_STATE, the oracle also models binary32 storage of the
+ * state: after every step the wake positions and strengths and the glider
+ * state are rounded to the nearest float (all arithmetic stays FP64). That
+ * variant measures how much of an FP32 path's error comes from storing the
+ * state in FP32 alone.
  */
 #include "vpm_oracle.h"
 
@@ -644,6 +650,14 @@ static void orc_step(const orc_params *p, orc_state *s, double dt, double u,
     gn[6] = g[6] + dt * acc[2];
   }
   memcpy(g, gn, sizeof(gn));
+#ifdef ORC_F32_STATE
+  for (int32_t i = 0; i < s->n_w; ++i) {
+    s->wx[i] = (float)s->wx[i];
+    s->wz[i] = (float)s->wz[i];
+    s->wg[i] = (float)s->wg[i];
+  }
+  for (int32_t i = 0; i < 7; ++i) g[i] = (float)g[i];
+#endif
   for (int32_t j = 0; j < nb; ++j) s->gb_prev[j] = gb[j];
 
   free(rc);

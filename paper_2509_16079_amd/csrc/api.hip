@@ -1,0 +1,185 @@
+// api.hip -- the C ABI declared in include/vpm.h: argument validation (pure
+// host code, runs before any HIP call), context management and dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "vpm_internal.h"
+
+namespace vpm {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+int fail(int code, const std::string &msg) {
+  g_error = msg;
+  return code;
+}
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_params(const vpm_params *p) {
+  if (!p) return fail(VPM_EINVAL, "params is NULL");
+  if (p->n_bound < 1 || p->n_bound > kMaxBound)
+    return fail(VPM_EINVAL, "n_bound must be in 1..64");
+  if (p->shed_mode < VPM_SHED_BOTH || p->shed_mode > VPM_SHED_NONE)
+    return fail(VPM_EINVAL, "unknown shed_mode");
+  if (p->precision != VPM_FP32C && p->precision != VPM_FP64)
+    return fail(VPM_EINVAL, "unknown precision");
+  if (!finite_pos(p->chord)) return fail(VPM_EINVAL, "chord must be > 0");
+  if (!(std::isfinite(p->shed_frac) && p->shed_frac >= 0.0))
+    return fail(VPM_EINVAL, "shed_frac must be >= 0");
+  if (!(std::isfinite(p->r_core) && p->r_core >= 1e-6))
+    return fail(VPM_EINVAL, "r_core must be >= 1e-6 m");
+  if (!(std::isfinite(p->decay) && p->decay >= 0.0))
+    return fail(VPM_EINVAL, "decay must be >= 0");
+  if (!finite_pos(p->mass) || !finite_pos(p->inertia))
+    return fail(VPM_EINVAL, "mass and inertia must be > 0");
+  const double f[] = {p->rho, p->span, p->grav, p->l_body, p->l_wing,
+                      p->l_elev, p->s_elev};
+  for (double v : f)
+    if (!std::isfinite(v)) return fail(VPM_EINVAL, "non-finite parameter");
+  return VPM_OK;
+}
+
+}  // namespace
+}  // namespace vpm
+
+using vpm::fail;
+
+extern "C" {
+
+VPM_API const char *vpm_last_error(void) { return vpm::g_error.c_str(); }
+
+VPM_API int vpm_validate_batch(const vpm_params *p, const vpm_batch_in *in,
+                               const vpm_batch_out *out) {
+  int rc = vpm::check_params(p);
+  if (rc != VPM_OK) return rc;
+  if (p->shed_mode != VPM_SHED_BOTH)
+    return fail(VPM_EINVAL, "vpm_rollout_batch supports shed_mode BOTH only");
+  if (!in || !out) return fail(VPM_EINVAL, "in or out is NULL");
+  if (in->K < 1 || in->H < 1) return fail(VPM_EINVAL, "K and H must be >= 1");
+  if (!vpm::finite_pos(in->dt)) return fail(VPM_EINVAL, "dt must be > 0");
+  if (in->n_fields < 1) return fail(VPM_EINVAL, "n_fields must be >= 1");
+  if (in->max_wake0 < 0) return fail(VPM_EINVAL, "max_wake0 must be >= 0");
+  if ((long long)in->max_wake0 + 2LL * in->H > (1LL << 30))
+    return fail(VPM_EINVAL, "max_wake0 + 2H too large");
+  if (in->n_pairs < 0 || in->n_pairs > vpm::kMaxPairs)
+    return fail(VPM_EINVAL, "n_pairs must be in 0..4");
+  if (in->n_pairs > 0 && !in->pairs)
+    return fail(VPM_EINVAL, "pairs is NULL with n_pairs > 0");
+  if (!in->g0 || !in->gb0 || !in->field_off || !in->wx || !in->wz ||
+      !in->wg || !in->u_mean || !in->u_eps)
+    return fail(VPM_EINVAL, "a required input pointer is NULL");
+  if (!in->field_of && in->n_fields < in->K)
+    return fail(VPM_EINVAL, "field_of is NULL but n_fields < K");
+  for (int i = 0; i < 7; ++i)
+    if (!std::isfinite(in->x_goal[i]) || !std::isfinite(in->q_diag[i]))
+      return fail(VPM_EINVAL, "non-finite x_goal or q_diag");
+  if (!out->g_final || !out->cost || !out->status)
+    return fail(VPM_EINVAL, "g_final, cost and status are required");
+  const bool any_wake = out->wx || out->wz || out->wg || out->vel_last;
+  if (any_wake && (!out->wake_off || !out->n_final))
+    return fail(VPM_EINVAL, "wake outputs need wake_off and n_final");
+  return VPM_OK;
+}
+
+VPM_API int vpm_create(vpm_ctx **out, int device) {
+  if (!out) return fail(VPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1)
+    return fail(VPM_EDEVICE, "no HIP device");
+  if (device < 0 || device >= n) return fail(VPM_EDEVICE, "no such device");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return fail(VPM_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(VPM_EDEVICE, std::string("device is ") + prop.gcnArchName +
+                                 ", this library is built for gfx950");
+  vpm_ctx *c = new (std::nothrow) vpm_ctx();
+  if (!c) return fail(VPM_ENOMEM, "context allocation failed");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  int lds = 0, optin = 0;
+  (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device);
+  c->max_lds = lds > optin ? lds : optin;
+  if (c->max_lds <= 0) c->max_lds = 65536;
+  *out = c;
+  return VPM_OK;
+}
+
+VPM_API void vpm_destroy(vpm_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (auto &kv : ctx->plate_cache) (void)hipFree(kv.second);
+  delete ctx;
+}
+
+VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
+                              const vpm_batch_in *in, vpm_batch_out *out,
+                              void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  int rc = vpm_validate_batch(params, in, out);
+  if (rc != VPM_OK) return rc;
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  const double *kinv = nullptr;
+  rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_BOTH, &kinv);
+  if (rc != VPM_OK) return rc;
+  return vpm::launch_rollout(ctx, params, in, out, kinv,
+                             static_cast<hipStream_t>(stream));
+}
+
+VPM_API int vpm_plate_solve(vpm_ctx *ctx, const vpm_params *params, int32_t B,
+                            const double *pose, const double *vw_c,
+                            const double *sum_gw, int32_t shed_mode,
+                            double *gamma_s, void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  int rc = vpm::check_params(params);
+  if (rc != VPM_OK) return rc;
+  if (shed_mode < VPM_SHED_BOTH || shed_mode > VPM_SHED_NONE)
+    return fail(VPM_EINVAL, "unknown shed_mode");
+  if (shed_mode == VPM_SHED_NONE && params->n_bound < 2)
+    return fail(VPM_EINVAL, "shed_mode NONE needs n_bound >= 2");
+  if (B < 0) return fail(VPM_EINVAL, "B must be >= 0");
+  if (B == 0) return VPM_OK;
+  if (!pose || !vw_c || !sum_gw || !gamma_s)
+    return fail(VPM_EINVAL, "a pointer is NULL");
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  const double *kinv = nullptr;
+  rc = vpm::plate_inverse_device(ctx, params, shed_mode, &kinv);
+  if (rc != VPM_OK) return rc;
+  return vpm::launch_plate_solve(params, B, pose, vw_c, sum_gw, shed_mode, kinv,
+                                 gamma_s, static_cast<hipStream_t>(stream));
+}
+
+VPM_API int mppi_weights(vpm_ctx *ctx, int32_t K, int32_t H, const double *cost,
+                         double lambda, const double *u_mean,
+                         const double *u_eps, double *w_out, double *u_new,
+                         int32_t *argmin, double *jmin, void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  if (K < 1 || H < 1) return fail(VPM_EINVAL, "K and H must be >= 1");
+  if (!vpm::finite_pos(lambda)) return fail(VPM_EINVAL, "lambda must be > 0");
+  if (!cost || !u_mean || !u_eps || !w_out || !u_new || !argmin || !jmin)
+    return fail(VPM_EINVAL, "a pointer is NULL");
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  return vpm::launch_mppi(K, H, cost, lambda, u_mean, u_eps, w_out, u_new,
+                          argmin, jmin, static_cast<hipStream_t>(stream));
+}
+
+VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,
+                               int32_t n_wake_max) {
+  int64_t total = 0, n = n0;
+  for (int32_t s = 0; s < H; ++s) {
+    const int64_t m = n + 2;
+    total += n * (2 * n_bound + 1) + m * (m - 1) + m * n_bound;
+    n = m;
+    if (n_wake_max > 0 && n > n_wake_max) n = n_wake_max;
+  }
+  return total;
+}
+
+}  // extern "C"

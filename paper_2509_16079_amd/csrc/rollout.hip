@@ -1,0 +1,662 @@
+// rollout.hip -- fused VPM-glider rollout kernel for gfx950.
+//
+// One workgroup (4 waves) owns one rollout for all H steps; the rollout's
+// wake lives in LDS for the whole horizon, so HBM is touched only to read
+// the initial state and controls and to write results. Per step
+// (Sec. III-A/B of the paper):
+//
+//   prologue (1 thread)  plate kinematics; disturbance termination (Sec. V)
+//   pass A   (4 waves)   every source = the wake at the start of the step;
+//                        every target = 2 N_b + 1 surface points (Eq. 12),
+//                        the two edge release points, and every wake vortex
+//                        (the wake part of Eq. 16). Sources are split into 4
+//                        contiguous quarters (one per wave); each lane keeps
+//                        T targets in registers and walks its quarter through
+//                        LDS broadcast reads. FP32 mode sums each 64-source
+//                        tile with plain FMAs and folds tiles into a
+//                        (sum, error) pair with TwoSum; the 4 quarters are
+//                        combined in FP64 in fixed order.
+//   solve    (wave 0)    Kelvin sum (FP64 wave reduction), RHS, FP64
+//                        Gamma_S = K^-1 b (Eq. 11) with the plate inverse
+//                        precomputed once per geometry; Bernoulli loads
+//                        (Eqs. 13-15) with an FP64 wave prefix scan;
+//                        elevator and rigid-body accelerations; shedding.
+//   pass B   (all)       each wake vortex adds the new LEV/TEV (regularised)
+//                        and bound (singular) terms -- completing Eq. 16 in
+//                        FIFO order -- then Euler advection and decay.
+//   epilogue (1 thread)  merge the two oldest above N_w,max; glider Euler.
+//
+// The N^2 work is pure VALU: 8 FP32 ops + 1 v_rsq_f32 per regularised pair,
+// no MFMA (the sum is not a dense contraction).
+#include <cmath>
+
+#include "vpm_internal.h"
+
+namespace vpm {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTile = 64;  // sources per compensation tile
+constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+
+struct alignas(16) Src32 {
+  float x, z, g, pad;  // position and circulation / (2 pi)
+};
+struct alignas(32) Src64 {
+  double x, z, g, pad;
+};
+template <typename R> struct SrcOf;
+template <> struct SrcOf<float> { using type = Src32; };
+template <> struct SrcOf<double> { using type = Src64; };
+
+template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
+
+// Kernel argument block, filled on the host.
+struct KArgs {
+  int K, H, nb, S, n_wake_max, max_wake0, n_pairs, cap, n_fields;
+  double dt, chord, shed_frac, r_core, decay, rho, span, grav, mass, inertia;
+  double l_body, l_wing, l_elev, s_elev;
+  double x_goal[7], q_diag[7];
+  const double *g0, *gb0, *wx, *wz, *wg, *u_mean, *u_eps, *kinv_t;
+  const int64_t *field_off;
+  const int32_t *field_of, *pairs;
+  double *g_final, *cost, *traj, *gamma_s, *wx_out, *wz_out, *wg_out;
+  double *vel_last;
+  int32_t *status, *n_final, *n_vel_last;
+  int64_t *pair_count;
+  const int64_t *wake_off;
+  int off_vsurf, off_red, off_vel, off_kinv;  // byte offsets into dynamic LDS
+};
+
+// Per-rollout scalars shared by the workgroup.
+template <typename R> struct Shared {
+  R g[7], gn[7];
+  R le[2], et[2], en[2], xw[2], xwd[2], lev[2], tev[2];
+  R bpos[kMaxBound][2];
+  R bgam[kMaxBound];
+  R shed_g[2];
+  double gb_prev[kMaxBound];
+  double bvec[kMaxBound + 2];
+  int head, n_w, status;
+  int pa[kMaxPairs], pb[kMaxPairs];
+  long long pairs;
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline float rsq(float d) { return __builtin_amdgcn_rsqf(d); }
+__device__ inline double rsq(double d) { return 1.0 / sqrt(d); }
+__device__ inline float rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ inline double rcp(double d) { return 1.0 / d; }
+
+// Regularised kernel (Eq. 5) times Gamma, with g = Gamma/(2 pi) folded in:
+// g (-dz, dx) / sqrt(rc^4 + r^4).
+template <typename R>
+__device__ inline void reg_term(R dx, R dz, R g, R rc4, R &vx, R &vz) {
+  R r2 = dx * dx + dz * dz;
+  R k = g * rsq(r2 * r2 + rc4);
+  vx -= dz * k;
+  vz += dx * k;
+}
+
+// Singular kernel (Eq. 4) times Gamma, g = Gamma/(2 pi): g (-dz, dx) / r^2;
+// a coincident point contributes 0.
+template <typename R>
+__device__ inline void sing_term(R dx, R dz, R g, R &vx, R &vz) {
+  R r2 = dx * dx + dz * dz;
+  R k = r2 > R(0) ? g * rcp(r2) : R(0);
+  vx -= dz * k;
+  vz += dx * k;
+}
+
+// Knuth's TwoSum: s + c absorbs t with the rounding error of s + t kept in c.
+__device__ inline void two_sum(float &s, float &c, float t) {
+  float u = s + t;
+  float bp = u - s;
+  float err = (s - (u - bp)) + (t - bp);
+  s = u;
+  c += err;
+}
+
+// Pass A over one wave's source range for the T targets of each lane.
+template <typename R, int T>
+__device__ void pass_a(const typename SrcOf<R>::type *__restrict__ src, int s_lo,
+                       int s_hi, const R (&tx)[T], const R (&tz)[T], R rc4,
+                       Vec2<R> *__restrict__ red, int lane) {
+  R sx[T], sz[T], cx[T], cz[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) sx[j] = sz[j] = cx[j] = cz[j] = R(0);
+  for (int s0 = s_lo; s0 < s_hi; s0 += kTile) {
+    const int s1 = min(s0 + kTile, s_hi);
+    R ax[T], az[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) ax[j] = az[j] = R(0);
+#pragma unroll 4
+    for (int q = s0; q < s1; ++q) {
+      const typename SrcOf<R>::type v = src[q];
+#pragma unroll
+      for (int j = 0; j < T; ++j) reg_term(tx[j] - v.x, tz[j] - v.z, v.g, rc4, ax[j], az[j]);
+    }
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        two_sum(sx[j], cx[j], ax[j]);
+        two_sum(sz[j], cz[j], az[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        sx[j] += ax[j];
+        sz[j] += az[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < T; ++j) red[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
+}
+
+template <typename R>
+__device__ inline void surface_point(const Shared<R> &sh, int t, int nb, R lb,
+                                     R ds, R c, R &px, R &pz) {
+  R s;
+  if (t <= nb)
+    s = R(t) * lb;  // collocation, LE to TE
+  else if (t < 2 * nb + 1)
+    s = (R(t - nb - 1) + R(0.5)) * lb;  // bound
+  else if (t == 2 * nb + 1)
+    s = -ds;  // LEV release point
+  else
+    s = c + ds;  // TEV release point
+  px = sh.le[0] + s * sh.et[0];
+  pz = sh.le[1] + s * sh.et[1];
+}
+
+template <typename R, int T>
+__device__ void pass_a_chunk(const KArgs &a, const Shared<R> &sh,
+                             const typename SrcOf<R>::type *src, Vec2<R> *red,
+                             int c0, int NT, int head, int s_lo, int s_hi,
+                             int lane, int wave) {
+  const int nb = a.nb, n_surf = 2 * nb + 3;
+  const R lb = R(a.chord / nb), ds = R(a.shed_frac * a.chord), c = R(a.chord);
+  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  R tx[T], tz[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int t = c0 + lane + 64 * j;
+    tx[j] = tz[j] = R(0);
+    if (t < NT) {
+      if (t < n_surf) {
+        surface_point(sh, t, nb, lb, ds, c, tx[j], tz[j]);
+      } else {
+        const auto v = src[head + t - n_surf];
+        tx[j] = v.x;
+        tz[j] = v.z;
+      }
+    }
+  }
+  pass_a<R, T>(src, s_lo, s_hi, tx, tz, rc4, red + wave * 64 * T, lane);
+}
+
+// Segment a-b against the chord rectangle inflated by 2 % of chord opposite
+// the normal (Sec. V), by Liang-Barsky clipping in plate coordinates.
+__device__ inline bool clip_slab(double p0, double d, double lo, double hi,
+                                 double &u0, double &u1) {
+  if (d == 0.0) return p0 >= lo && p0 <= hi;
+  double ta = (lo - p0) / d, tb = (hi - p0) / d;
+  if (ta > tb) {
+    double t = ta;
+    ta = tb;
+    tb = t;
+  }
+  u0 = fmax(u0, ta);
+  u1 = fmin(u1, tb);
+  return u0 <= u1;
+}
+
+template <typename R>
+__device__ bool hits_plate(const Shared<R> &sh, double c, double ax, double az,
+                           double bx, double bz) {
+  const double lx = sh.le[0], lz = sh.le[1];
+  const double tx = sh.et[0], tz = sh.et[1], nx = sh.en[0], nz = sh.en[1];
+  double sa = (ax - lx) * tx + (az - lz) * tz, ha = (ax - lx) * nx + (az - lz) * nz;
+  double sb = (bx - lx) * tx + (bz - lz) * tz, hb = (bx - lx) * nx + (bz - lz) * nz;
+  double u0 = 0.0, u1 = 1.0;
+  if (!clip_slab(sa, sb - sa, 0.0, c, u0, u1)) return false;
+  return clip_slab(ha, hb - ha, -0.02 * c, 0.0, u0, u1);
+}
+
+template <typename R>
+__device__ void geometry(const KArgs &a, Shared<R> &sh) {
+  const R th = sh.g[2], thd = sh.g[6], lw = R(a.l_wing);
+  const R ct = cos(th), st = sin(th);
+  const R hc = R(0.5 * a.chord), ds = R(a.shed_frac * a.chord);
+  sh.xw[0] = sh.g[0] - lw * ct;
+  sh.xw[1] = sh.g[1] - lw * st;
+  sh.xwd[0] = sh.g[4] + lw * thd * st;
+  sh.xwd[1] = sh.g[5] - lw * thd * ct;
+  sh.et[0] = -ct;
+  sh.et[1] = -st;
+  sh.en[0] = -st;
+  sh.en[1] = ct;
+  sh.le[0] = sh.xw[0] + hc * ct;
+  sh.le[1] = sh.xw[1] + hc * st;
+  sh.lev[0] = sh.le[0] - ds * sh.et[0];
+  sh.lev[1] = sh.le[1] - ds * sh.et[1];
+  const R s_tev = R(a.chord) + ds;
+  sh.tev[0] = sh.le[0] + s_tev * sh.et[0];
+  sh.tev[1] = sh.le[1] + s_tev * sh.et[1];
+}
+
+template <typename R>
+__device__ void prologue(const KArgs &a, Shared<R> &sh,
+                         typename SrcOf<R>::type *src) {
+  geometry(a, sh);
+  for (int q = 0; q < kMaxPairs; ++q) {
+    const int pa = sh.pa[q], pb = sh.pb[q];
+    if (pa < 0) continue;
+    if (hits_plate(sh, a.chord, src[pa].x, src[pa].z, src[pb].x, src[pb].z)) {
+      src[pa].g = R(0);
+      src[pb].g = R(0);
+      sh.pa[q] = sh.pb[q] = -1;
+    }
+  }
+}
+
+// MINW: waves per SIMD the register budget must allow (4 for FP32 fills a CU
+// with four rollouts; FP64 takes 2 to avoid spills).
+template <typename R, int TMAX, int MINW>
+__global__ __launch_bounds__(kThreads, MINW) void rollout_kernel(KArgs a) {
+  using Src = typename SrcOf<R>::type;
+  extern __shared__ __align__(32) unsigned char lds[];
+  __shared__ Shared<R> sh;
+  Src *src = reinterpret_cast<Src *>(lds);
+  double2 *vsurf = reinterpret_cast<double2 *>(lds + a.off_vsurf);
+  Vec2<R> *red = reinterpret_cast<Vec2<R> *>(lds + a.off_red);
+  Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(lds + a.off_vel);
+  double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
+
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = a.nb, S = a.S, nc = nb + 1, n_surf = 2 * nb + 3;
+  const double dt = a.dt, lb = a.chord / nb;
+
+  const int fo = a.field_of ? a.field_of[k] : k;
+  const bool bad_field = fo < 0 || fo >= a.n_fields;
+  const int64_t f0 = bad_field ? 0 : a.field_off[fo];
+  const int n0 = bad_field ? -1 : static_cast<int>(a.field_off[fo + 1] - f0);
+  if (n0 < 0 || n0 > a.max_wake0) {  // uniform over the workgroup
+    if (tid < 7) a.g_final[7 * k + tid] = a.g0[7 * k + tid];
+    if (tid == 0) {
+      a.cost[k] = INFINITY;
+      a.status[k] = n0 < 0 ? VPM_ROLLOUT_BADFIELD : VPM_ROLLOUT_CAPACITY;
+      if (a.pair_count) a.pair_count[k] = 0;
+      if (a.n_final) a.n_final[k] = 0;
+      if (a.n_vel_last) a.n_vel_last[k] = 0;
+    }
+    return;
+  }
+
+  for (int q = tid; q < n0; q += kThreads)
+    src[q] = Src{R(a.wx[f0 + q]), R(a.wz[f0 + q]), R(a.wg[f0 + q] * kInv2Pi), R(0)};
+  for (int q = tid; q < S * S; q += kThreads) kinv[q] = a.kinv_t[q];
+  if (tid < 7) {
+    sh.g[tid] = R(a.g0[7 * k + tid]);
+    if (a.traj) a.traj[(size_t)k * (a.H + 1) * 7 + tid] = a.g0[7 * k + tid];
+  }
+  if (tid < nb) sh.gb_prev[tid] = a.gb0[(size_t)k * nb + tid];
+  if (tid == 0) {
+    sh.head = 0;
+    sh.n_w = n0;
+    sh.status = 0;
+    sh.pairs = 0;
+    for (int q = 0; q < kMaxPairs; ++q) {
+      int pa = -1, pb = -1;
+      if (q < a.n_pairs && a.pairs) {
+        pa = a.pairs[(size_t)k * 2 * a.n_pairs + 2 * q];
+        pb = a.pairs[(size_t)k * 2 * a.n_pairs + 2 * q + 1];
+        if (pa < 0 || pb < 0 || pa >= n0 || pb >= n0 || pa == pb) pa = pb = -1;
+      }
+      sh.pa[q] = pa;
+      sh.pb[q] = pb;
+    }
+  }
+  __syncthreads();
+
+  const R one_decay = R(1.0 - a.decay * dt);
+  const R dtr = R(dt);
+  for (int n = 0; n < a.H; ++n) {
+    // ---- prologue (thread 0): kinematics and disturbance termination; for
+    // n > 0 it follows the previous step's epilogue in the same section
+    if (n == 0) {
+      if (tid == 0) prologue(a, sh, src);
+      __syncthreads();
+    }
+    const int head = sh.head, n_w = sh.n_w;
+    const int NT = n_surf + n_w;
+
+    // ---- pass A: wake sources onto surface, release and wake targets
+    const int s_lo = head + (n_w * wave) / kWaves;
+    const int s_hi = head + (n_w * (wave + 1)) / kWaves;
+    for (int c0 = 0; c0 < NT;) {
+      const int rem = NT - c0;
+      int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
+      while (T > 1 && 64 * T > rem) T >>= 1;
+      switch (T) {
+        case 1: pass_a_chunk<R, 1>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+        case 2: if constexpr (TMAX >= 2) pass_a_chunk<R, 2>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+        case 4: if constexpr (TMAX >= 4) pass_a_chunk<R, 4>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+        default: if constexpr (TMAX >= 8) pass_a_chunk<R, 8>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+      }
+      __syncthreads();
+      const int span = 64 * T;
+      for (int t = tid; t < span && c0 + t < NT; t += kThreads) {
+        double vx = 0.0, vz = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          const Vec2<R> r = red[w * span + t];
+          vx += double(r.x);
+          vz += double(r.z);
+        }
+        const int tt = c0 + t;
+        if (tt < n_surf)
+          vsurf[tt] = make_double2(vx, vz);
+        else
+          vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};
+      }
+      __syncthreads();
+      c0 += span;
+    }
+
+    // ---- wave 0: Kelvin sum, surface solve, loads, dynamics, shedding
+    if (wave == 0) {
+      double sg = 0.0;
+      for (int q = lane; q < n_w; q += 64) sg += double(src[head + q].g);
+      const double sum_gw = kTwoPi * wave_sum(sg);
+      const double lex = sh.le[0], lez = sh.le[1], etx = sh.et[0], etz = sh.et[1];
+      const double enx = sh.en[0], enz = sh.en[1];
+      const double xwx = sh.xw[0], xwz = sh.xw[1], thd = sh.g[6];
+      const double xwdx = sh.xwd[0], xwdz = sh.xwd[1];
+      // b_i = -v~(r_ci).n with v~ = v_W - xw_dot - thd J(r - x_w) (Eq. 12)
+      auto rhs = [&](int r) -> double {
+        if (r >= S) return 0.0;
+        if (r == S - 1) return -sum_gw;
+        const double px = lex + r * lb * etx, pz = lez + r * lb * etz;
+        const double2 vw = vsurf[r];
+        const double vx = vw.x - xwdx + thd * (pz - xwz);
+        const double vz = vw.y - xwdz - thd * (px - xwx);
+        return -(vx * enx + vz * enz);
+      };
+      if (lane < S) sh.bvec[lane] = rhs(lane);
+      if (lane + 64 < S) sh.bvec[lane + 64] = rhs(lane + 64);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // Gamma_S = K^-1 b (Eq. 11): lane i owns rows i and i + 64
+      double gam0 = 0.0, gam1 = 0.0;
+      const int i0 = lane < S ? lane : 0, i1 = lane + 64 < S ? lane + 64 : 0;
+#pragma unroll 8
+      for (int j = 0; j < S; ++j) {
+        const double bj = sh.bvec[j];
+        gam0 += kinv[j * S + i0] * bj;
+        gam1 += kinv[j * S + i1] * bj;
+      }
+      auto row = [&](int r) -> double {
+        return r < 64 ? __shfl(gam0, r, 64) : __shfl(gam1, r - 64, 64);
+      };
+      const double glev = row(nb), gtev = row(nb + 1);
+      if (a.gamma_s) {
+        double *gs = a.gamma_s + ((size_t)k * a.H + n) * S;
+        if (lane < S) gs[lane] = gam0;
+        if (lane + 64 < S) gs[lane + 64] = gam1;
+      }
+      // Eqs. 13-15. With P_j the prefix sums of Gamma_b, the force needs
+      // sum_j (P_j - P'_j) = sum_k (N_b - k) dGamma_k and the moment
+      // sum_j arm_j (P_j - P'_j) = sum_k A_k dGamma_k, A_k = sum_{j>=k} arm_j
+      // = -(N_b - k) k l_b / 2 (arm_j = c/2 - (j + 1/2) l_b): two plain sums.
+      const bool on = lane < nb;
+      const double gbj = on ? gam0 : 0.0;
+      const double dgb = on ? gam0 - sh.gb_prev[lane] : 0.0;
+      const double sj = (lane + 0.5) * lb;
+      const double bx = lex + sj * etx, bz = lez + sj * etz;
+      const double2 vb = on ? vsurf[nc + lane] : make_double2(0.0, 0.0);
+      const double vtx = vb.x - xwdx + thd * (bz - xwz);
+      const double vtz = vb.y - xwdz - thd * (bx - xwx);
+      const double qt = vtx * etx + vtz * etz;
+      const double arm = 0.5 * a.chord - sj;
+      const double local = (gbj / lb) * qt + glev / dt;
+      const double tf = on ? local + (nb - lane) * dgb / dt : 0.0;
+      const double tm = on ? arm * local - 0.5 * (nb - lane) * lane * lb * dgb / dt : 0.0;
+      const double sdp = a.rho * wave_sum(tf);
+      const double sarm = a.rho * wave_sum(tm);
+      if (on) {
+        sh.gb_prev[lane] = gbj;
+        sh.bpos[lane][0] = R(bx);
+        sh.bpos[lane][1] = R(bz);
+        sh.bgam[lane] = R(gbj * kInv2Pi);
+      }
+      if (lane == 0) {
+        const double fwx = lb * a.span * sdp * enx, fwz = lb * a.span * sdp * enz;
+        const double mw = lb * a.span * sarm;
+        // Sec. III-B: elevator force and rigid-body accelerations
+        const R x = sh.g[0], z = sh.g[1], th = sh.g[2], ph = sh.g[3];
+        const R xd = sh.g[4], zd = sh.g[5], thr = sh.g[6];
+        const R u = R(a.u_mean[n] + a.u_eps[(size_t)k * a.H + n]);
+        const R l = R(a.l_body), le = R(a.l_elev);
+        const R ct = cos(th), st = sin(th), ctp = cos(th + ph), stp = sin(th + ph);
+        const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
+        const R xed = xd + l * thr * st + le * (thr + u) * stp;
+        const R zed = zd - l * thr * ct - le * (thr + u) * ctp;
+        const R alpha = th + ph - atan2(zed, xed);
+        const R fe = R(0.5 * a.rho * a.s_elev) * (xed * xed + zed * zed) * R(2) * sin(alpha);
+        const R fex = -fe * stp, fez = fe * ctp;
+        const R fx = R(fwx) + fex, fz = R(fwz) + fez;
+        const R ax_ = fx / R(a.mass);
+        const R az_ = fz / R(a.mass) - R(a.grav);
+        const R mom = (sh.xw[0] - x) * R(fwz) - (sh.xw[1] - z) * R(fwx) +
+                      (xe - x) * fez - (ze - z) * fex + R(mw);
+        const R ath = mom / R(a.inertia);
+        sh.gn[0] = x + dtr * xd;
+        sh.gn[1] = z + dtr * zd;
+        sh.gn[2] = th + dtr * thr;
+        sh.gn[3] = ph + dtr * u;
+        sh.gn[4] = xd + dtr * ax_;
+        sh.gn[5] = zd + dtr * az_;
+        sh.gn[6] = thr + dtr * ath;
+        // shedding: LEV then TEV join the wake tail (Sec. III-A)
+        const int p = head + n_w;
+        sh.shed_g[0] = R(glev * kInv2Pi);
+        sh.shed_g[1] = R(gtev * kInv2Pi);
+        src[p] = Src{sh.lev[0], sh.lev[1], sh.shed_g[0], R(0)};
+        src[p + 1] = Src{sh.tev[0], sh.tev[1], sh.shed_g[1], R(0)};
+        const double2 vl = vsurf[2 * nb + 1], vt = vsurf[2 * nb + 2];
+        vel[p] = Vec2<R>{R(vl.x), R(vl.y)};
+        vel[p + 1] = Vec2<R>{R(vt.x), R(vt.y)};
+      }
+    }
+    __syncthreads();
+
+    // ---- pass B: edge and bound terms (FIFO order), then advect and decay
+    const int m = n_w + 2;
+    const bool last = (n == a.H - 1);
+    const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+    for (int t = tid; t < m; t += kThreads) {
+      const int p = head + t;
+      Src s = src[p];
+      const Vec2<R> v0 = vel[p];
+      R ex = R(0), ez = R(0);
+      reg_term(s.x - sh.lev[0], s.z - sh.lev[1], sh.shed_g[0], rc4, ex, ez);
+      reg_term(s.x - sh.tev[0], s.z - sh.tev[1], sh.shed_g[1], rc4, ex, ez);
+      for (int j = 0; j < nb; ++j)
+        sing_term(s.x - sh.bpos[j][0], s.z - sh.bpos[j][1], sh.bgam[j], ex, ez);
+      const double vx = double(v0.x) + double(ex), vz = double(v0.z) + double(ez);
+      if (last && a.vel_last) {
+        double *o = a.vel_last + 2 * (a.wake_off[k] + t);
+        o[0] = vx;
+        o[1] = vz;
+      }
+      s.x = s.x + dtr * R(vx);
+      s.z = s.z + dtr * R(vz);
+      s.g = s.g * one_decay;
+      src[p] = s;
+    }
+    __syncthreads();
+
+    // ---- epilogue: merging and the glider step
+    if (tid == 0) {
+      sh.pairs += (long long)n_w * (2 * nb + 1) + (long long)m * (m - 1) +
+                  (long long)m * nb;
+      int h = sh.head, cnt = m;
+      while (a.n_wake_max > 0 && cnt > a.n_wake_max && cnt >= 2) {
+        const Src s0 = src[h], s1 = src[h + 1];
+        src[h + 1] = Src{R(0.5) * (s0.x + s1.x), R(0.5) * (s0.z + s1.z), s0.g + s1.g, R(0)};
+        for (int q = 0; q < kMaxPairs; ++q)
+          if (sh.pa[q] == h || sh.pa[q] == h + 1 || sh.pb[q] == h || sh.pb[q] == h + 1)
+            sh.pa[q] = sh.pb[q] = -1;
+        ++h;
+        --cnt;
+      }
+      sh.head = h;
+      sh.n_w = cnt;
+      for (int i = 0; i < 7; ++i) sh.g[i] = sh.gn[i];
+      if (a.traj)
+        for (int i = 0; i < 7; ++i)
+          a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
+      if (last && a.n_vel_last) a.n_vel_last[k] = m;
+      if (!last) prologue(a, sh, src);
+    }
+    __syncthreads();
+  }
+
+  // ---- outputs
+  if (tid == 0) {
+    bool finite = true;
+    double j = 0.0;
+    for (int i = 0; i < 7; ++i) {
+      const double gi = double(sh.g[i]);
+      a.g_final[7 * k + i] = gi;
+      if (!isfinite(gi)) finite = false;
+      const double d = gi - a.x_goal[i];
+      j += a.q_diag[i] * d * d;
+    }
+    a.cost[k] = finite ? j : INFINITY;
+    a.status[k] = sh.status | (finite ? 0 : VPM_ROLLOUT_NONFINITE);
+    if (a.pair_count) a.pair_count[k] = sh.pairs;
+    if (a.n_final) a.n_final[k] = sh.n_w;
+  }
+  if (a.wake_off) {
+    const int64_t o = a.wake_off[k];
+    const int capo = static_cast<int>(a.wake_off[k + 1] - o);
+    const int cnt = min(sh.n_w, capo);
+    for (int t = tid; t < cnt; t += kThreads) {
+      const Src s = src[sh.head + t];
+      if (a.wx_out) a.wx_out[o + t] = double(s.x);
+      if (a.wz_out) a.wz_out[o + t] = double(s.z);
+      if (a.wg_out) a.wg_out[o + t] = double(s.g) * kTwoPi;
+    }
+  }
+}
+
+template <typename R>
+int lds_layout(int cap, int nb, int tmax, KArgs &a) {
+  size_t off = 0;
+  off += (size_t)cap * sizeof(typename SrcOf<R>::type);
+  off = (off + 15) & ~size_t(15);
+  a.off_kinv = static_cast<int>(off);
+  off += (size_t)a.S * a.S * sizeof(double);
+  a.off_vsurf = static_cast<int>(off);
+  off += (size_t)(2 * nb + 3) * sizeof(double2);
+  a.off_red = static_cast<int>(off);
+  off += (size_t)kWaves * 64 * tmax * sizeof(Vec2<R>);
+  a.off_vel = static_cast<int>(off);
+  off += (size_t)cap * sizeof(Vec2<R>);
+  return static_cast<int>(off);
+}
+
+template <typename R, int TMAX, int MINW>
+int launch_t(vpm_ctx *ctx, KArgs &a, hipStream_t stream) {
+  const int lds = lds_layout<R>(a.cap, a.nb, TMAX, a);
+  const int static_lds = static_cast<int>(sizeof(Shared<R>));
+  if (lds + static_lds > ctx->max_lds)
+    return fail(VPM_ECAPACITY,
+                "wake capacity " + std::to_string(a.cap) + " needs " +
+                    std::to_string(lds + static_lds) + " B of LDS, limit " +
+                    std::to_string(ctx->max_lds));
+  auto kern = rollout_kernel<R, TMAX, MINW>;
+  if (lds > 65536)
+    VPM_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    lds));
+  hipLaunchKernelGGL(kern, dim3(a.K), dim3(kThreads), lds, stream, a);
+  VPM_HIP_TRY(hipGetLastError());
+  return VPM_OK;
+}
+
+}  // namespace
+
+int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
+                   vpm_batch_out *out, const double *kinv_t,
+                   hipStream_t stream) {
+  KArgs a{};
+  a.K = in->K;
+  a.H = in->H;
+  a.nb = p->n_bound;
+  a.S = system_size(p->n_bound, VPM_SHED_BOTH);
+  a.n_wake_max = p->n_wake_max;
+  a.max_wake0 = in->max_wake0;
+  a.n_pairs = in->n_pairs;
+  a.n_fields = in->n_fields;
+  a.cap = in->max_wake0 + 2 * in->H;
+  a.dt = in->dt;
+  a.chord = p->chord;
+  a.shed_frac = p->shed_frac;
+  a.r_core = p->r_core;
+  a.decay = p->decay;
+  a.rho = p->rho;
+  a.span = p->span;
+  a.grav = p->grav;
+  a.mass = p->mass;
+  a.inertia = p->inertia;
+  a.l_body = p->l_body;
+  a.l_wing = p->l_wing;
+  a.l_elev = p->l_elev;
+  a.s_elev = p->s_elev;
+  for (int i = 0; i < 7; ++i) {
+    a.x_goal[i] = in->x_goal[i];
+    a.q_diag[i] = in->q_diag[i];
+  }
+  a.g0 = in->g0;
+  a.gb0 = in->gb0;
+  a.wx = in->wx;
+  a.wz = in->wz;
+  a.wg = in->wg;
+  a.u_mean = in->u_mean;
+  a.u_eps = in->u_eps;
+  a.kinv_t = kinv_t;
+  a.field_off = in->field_off;
+  a.field_of = in->field_of;
+  a.pairs = in->n_pairs > 0 ? in->pairs : nullptr;
+  a.g_final = out->g_final;
+  a.cost = out->cost;
+  a.traj = out->traj;
+  a.gamma_s = out->gamma_s;
+  a.status = out->status;
+  a.pair_count = out->pair_count;
+  const bool wake = out->wake_off && out->n_final;
+  a.wake_off = wake ? out->wake_off : nullptr;
+  a.n_final = out->n_final;
+  a.wx_out = wake ? out->wx : nullptr;
+  a.wz_out = wake ? out->wz : nullptr;
+  a.wg_out = wake ? out->wg : nullptr;
+  a.vel_last = wake ? out->vel_last : nullptr;
+  a.n_vel_last = out->n_vel_last;
+  if (p->precision == VPM_FP64) return launch_t<double, 2, 2>(ctx, a, stream);
+  return launch_t<float, 4, 4>(ctx, a, stream);
+}
+
+}  // namespace vpm

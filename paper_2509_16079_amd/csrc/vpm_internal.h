@@ -1,0 +1,83 @@
+// vpm_internal.h -- private declarations of the gfx950 rollout library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "vpm.h"
+
+namespace vpm {
+
+// Per-thread error message and a helper that records it.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define VPM_HIP_TRY(expr)                                                   \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess)                                                   \
+      return ::vpm::fail(VPM_EDEVICE, std::string(#expr ": ") +             \
+                                          hipGetErrorString(_e));           \
+  } while (0)
+
+constexpr int kMaxPairs = 4;
+constexpr int kMaxBound = 64;
+
+// System size per shedding mode (bound unknowns, then LEV, then TEV).
+inline int system_size(int nb, int mode) {
+  return mode == VPM_SHED_BOTH ? nb + 2 : mode == VPM_SHED_TE ? nb + 1 : nb;
+}
+// First collocation row of the system per mode (LE row dropped unless BOTH).
+inline int first_row(int mode) { return mode == VPM_SHED_BOTH ? 0 : 1; }
+
+// Host FP64: inverse of the surface matrix in the plate's body frame,
+// returned transposed (column j of the inverse is contiguous) so that lane
+// i of a wave reading entry (i, j) touches consecutive addresses.
+// Returns VPM_OK or VPM_ESINGULAR.
+int plate_inverse_T(int nb, double chord, double shed_frac, double r_core,
+                    int mode, std::vector<double> &inv_t);
+
+struct PlateKey {
+  int nb, mode;
+  double chord, shed_frac, r_core;
+  bool operator<(const PlateKey &o) const {
+    return std::tie(nb, mode, chord, shed_frac, r_core) <
+           std::tie(o.nb, o.mode, o.chord, o.shed_frac, o.r_core);
+  }
+};
+
+}  // namespace vpm
+
+struct vpm_ctx {
+  int device = 0;
+  int max_lds = 65536;      // dynamic LDS bytes one workgroup may use
+  int n_cu = 0;
+  std::mutex mu;
+  std::map<vpm::PlateKey, double *> plate_cache;  // device inverses
+};
+
+namespace vpm {
+
+// Device inverse for a plate (cached in the context).
+int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
+                         const double **out);
+
+int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
+                   vpm_batch_out *out, const double *kinv_t,
+                   hipStream_t stream);
+int launch_plate_solve(const vpm_params *p, int B, const double *pose,
+                       const double *vw_c, const double *sum_gw, int mode,
+                       const double *kinv_t, double *gamma_s,
+                       hipStream_t stream);
+int launch_mppi(int K, int H, const double *cost, double lambda,
+                const double *u_mean, const double *u_eps, double *w_out,
+                double *u_new, int32_t *argmin, double *jmin,
+                hipStream_t stream);
+
+}  // namespace vpm

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of ``libvpm.so`` (the C ABI of ``include/vpm.h``).
+
+Only argument marshalling happens here: PyTorch provides device memory and
+streams, and every step of the rollout runs in the library's HIP kernels.
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvpm.so")
+
+OK, PENDING = 0, 1
+EINVAL, ENOMEM, EDEVICE, ESINGULAR, EBUDGET, ECAPACITY, ENOTFOUND = -1, -2, -3, -4, -5, -6, -7
+ROLLOUT_NONFINITE, ROLLOUT_CAPACITY, ROLLOUT_BADFIELD = 1, 2, 4
+SHED_BOTH, SHED_TE, SHED_NONE = 0, 1, 2
+FP32C, FP64 = 0, 1
+
+_P = C.c_void_p
+_D = C.c_double
+_I = C.c_int32
+
+
+class Params(C.Structure):
+    _fields_ = [("n_bound", _I), ("n_wake_max", _I), ("shed_mode", _I), ("precision", _I),
+                ("chord", _D), ("shed_frac", _D), ("r_core", _D), ("decay", _D), ("rho", _D),
+                ("span", _D), ("grav", _D), ("mass", _D), ("inertia", _D), ("l_body", _D),
+                ("l_wing", _D), ("l_elev", _D), ("s_elev", _D)]
+
+
+class BatchIn(C.Structure):
+    _fields_ = [("K", _I), ("H", _I), ("dt", _D), ("n_fields", _I), ("max_wake0", _I),
+                ("n_pairs", _I), ("reserved", _I), ("g0", _P), ("gb0", _P), ("field_off", _P),
+                ("field_of", _P), ("wx", _P), ("wz", _P), ("wg", _P), ("pairs", _P),
+                ("u_mean", _P), ("u_eps", _P), ("x_goal", _D * 7), ("q_diag", _D * 7)]
+
+
+class BatchOut(C.Structure):
+    _fields_ = [("g_final", _P), ("cost", _P), ("status", _P), ("traj", _P), ("gamma_s", _P),
+                ("pair_count", _P), ("wake_off", _P), ("wx", _P), ("wz", _P), ("wg", _P),
+                ("n_final", _P), ("vel_last", _P), ("n_vel_last", _P)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libvpm.so is not built: run `python -m paper_2509_16079_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.vpm_last_error.restype = C.c_char_p
+        L.vpm_create.argtypes = [C.POINTER(_P), C.c_int]
+        L.vpm_destroy.argtypes = [_P]
+        L.vpm_destroy.restype = None
+        L.vpm_validate_batch.argtypes = [C.POINTER(Params), C.POINTER(BatchIn), C.POINTER(BatchOut)]
+        L.vpm_rollout_batch.argtypes = [_P, C.POINTER(Params), C.POINTER(BatchIn),
+                                        C.POINTER(BatchOut), _P]
+        L.vpm_plate_solve.argtypes = [_P, C.POINTER(Params), _I, _P, _P, _P, _I, _P, _P]
+        L.mppi_weights.argtypes = [_P, _I, _I, _P, _D, _P, _P, _P, _P, _P, _P, _P]
+        L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
+        L.vpm_pair_count.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+class VpmError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().vpm_last_error().decode()
+        super().__init__(f"{where} failed with status {code}: {msg}")
+        self.code = code
+
+
+def check(code, where):
+    if code < 0:
+        raise VpmError(code, where)
+    return code
+
+
+def make_params(d: dict, precision=FP32C) -> Params:
+    p = Params()
+    for name, _ in Params._fields_:
+        if name == "precision":
+            p.precision = precision
+        else:
+            setattr(p, name, d[name])
+    return p
+
+
+def pair_count(n0, H, n_bound, n_wake_max):
+    return int(lib().vpm_pair_count(int(n0), int(H), int(n_bound), int(n_wake_max)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceBatch:
+    """The inputs of one rollout batch, resident on the GPU as torch tensors."""
+
+    def __init__(self, wl, device="cuda"):
+        import torch
+        dd = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        self.wl = wl
+        self.K, self.H, self.dt = wl.K, wl.H, wl.dt
+        self.g0 = dd(wl.g0)
+        self.gb0 = dd(wl.gb0)
+        self.field_off = dd(wl.field_off, torch.int64)
+        self.field_of = dd(wl.field_of, torch.int32)
+        n = max(1, len(wl.wx))
+        pad = lambda a: np.concatenate([a, np.zeros(n - len(a))]) if len(a) < n else a
+        self.wx, self.wz, self.wg = dd(pad(wl.wx)), dd(pad(wl.wz)), dd(pad(wl.wg))
+        self.n_pairs = wl.pairs.shape[1] // 2 if wl.pairs is not None else 0
+        self.pairs = dd(wl.pairs, torch.int32) if self.n_pairs else None
+        self.u_mean = dd(wl.u_mean)
+        self.u_eps = dd(wl.u_eps)
+        self.n_fields = len(wl.field_off) - 1
+        sizes = np.diff(wl.field_off)
+        self.max_wake0 = int(sizes.max()) if sizes.size else 0
+
+    def batch_in(self) -> BatchIn:
+        b = BatchIn()
+        b.K, b.H, b.dt = self.K, self.H, self.dt
+        b.n_fields, b.max_wake0, b.n_pairs = self.n_fields, self.max_wake0, self.n_pairs
+        b.g0, b.gb0, b.field_off, b.field_of = (_ptr(self.g0), _ptr(self.gb0),
+                                                _ptr(self.field_off), _ptr(self.field_of))
+        b.wx, b.wz, b.wg = _ptr(self.wx), _ptr(self.wz), _ptr(self.wg)
+        b.pairs = _ptr(self.pairs)
+        b.u_mean, b.u_eps = _ptr(self.u_mean), _ptr(self.u_eps)
+        for i in range(7):
+            b.x_goal[i] = float(self.wl.x_goal[i])
+            b.q_diag[i] = float(self.wl.q_diag[i])
+        return b
+
+
+class DeviceOutputs:
+    """Output buffers of one rollout batch (torch tensors on the GPU)."""
+
+    def __init__(self, db: DeviceBatch, *, traj=False, gamma_s=False, pair_count=True,
+                 final_wake=False, vel_last=False, device="cuda"):
+        import torch
+        K, H = db.K, db.H
+        nb = db.wl.params["n_bound"]
+        f64 = dict(dtype=torch.float64, device=device)
+        self.g_final = torch.empty((K, 7), **f64)
+        self.cost = torch.empty(K, **f64)
+        self.status = torch.empty(K, dtype=torch.int32, device=device)
+        self.traj = torch.empty((K, H + 1, 7), **f64) if traj else None
+        self.gamma_s = torch.empty((K, H, nb + 2), **f64) if gamma_s else None
+        self.pair_count = torch.empty(K, dtype=torch.int64, device=device) if pair_count else None
+        self.wake_off = self.wx = self.wz = self.wg = self.n_final = None
+        self.vel_last = self.n_vel_last = None
+        if final_wake or vel_last:
+            cap = db.wl.n0 + 2 * H
+            off = np.zeros(K + 1, dtype=np.int64)
+            off[1:] = np.cumsum(cap)
+            self.wake_off_np = off
+            self.wake_off = torch.as_tensor(off, device=device)
+            tot = int(off[-1])
+            self.n_final = torch.empty(K, dtype=torch.int32, device=device)
+            if final_wake:
+                self.wx = torch.empty(tot, **f64)
+                self.wz = torch.empty(tot, **f64)
+                self.wg = torch.empty(tot, **f64)
+            if vel_last:
+                self.vel_last = torch.empty((tot, 2), **f64)
+                self.n_vel_last = torch.empty(K, dtype=torch.int32, device=device)
+
+    def batch_out(self) -> BatchOut:
+        o = BatchOut()
+        for name, _ in BatchOut._fields_:
+            setattr(o, name, _ptr(getattr(self, name)))
+        return o
+
+    def to_numpy(self) -> dict:
+        out = {}
+        for name in ("g_final", "cost", "status", "traj", "gamma_s", "pair_count", "wx", "wz",
+                     "wg", "n_final", "vel_last", "n_vel_last"):
+            t = getattr(self, name)
+            if t is not None:
+                out[name] = t.cpu().numpy()
+        if self.wake_off is not None:
+            out["out_off"] = self.wake_off_np
+        return out
+
+
+class Context:
+    """A library context on one GPU (``vpm_create`` / ``vpm_destroy``)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(lib().vpm_create(C.byref(h), int(device)), "vpm_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().vpm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rollout(self, params: dict, db: DeviceBatch, out: DeviceOutputs, precision=FP32C,
+                stream=None):
+        """Enqueue ``vpm_rollout_batch`` on ``stream`` (default: torch's current)."""
+        p = make_params(params, precision)
+        bi, bo = db.batch_in(), out.batch_out()
+        check(lib().vpm_rollout_batch(self.h, C.byref(p), C.byref(bi), C.byref(bo),
+                                      _stream_handle(stream)), "vpm_rollout_batch")
+        return out
+
+    def plate_solve(self, params: dict, pose, vw_c, sum_gw, shed_mode=SHED_BOTH, stream=None):
+        """FP64 surface solve for B poses (torch float64 CUDA tensors)."""
+        import torch
+        B = pose.shape[0]
+        S = params["n_bound"] + {SHED_BOTH: 2, SHED_TE: 1, SHED_NONE: 0}[shed_mode]
+        gs = torch.empty((B, S), dtype=torch.float64, device=pose.device)
+        p = make_params(params, FP64)
+        check(lib().vpm_plate_solve(self.h, C.byref(p), B, _ptr(pose), _ptr(vw_c), _ptr(sum_gw),
+                                    shed_mode, _ptr(gs), _stream_handle(stream)), "vpm_plate_solve")
+        return gs
+
+    def mppi(self, cost, lam, u_mean, u_eps, stream=None):
+        """MPPI weights and update; returns (w, u_new, argmin, jmin) tensors."""
+        import torch
+        K, H = u_eps.shape
+        dev = cost.device
+        w = torch.empty(K, dtype=torch.float64, device=dev)
+        u_new = torch.empty(H, dtype=torch.float64, device=dev)
+        am = torch.empty(1, dtype=torch.int32, device=dev)
+        jm = torch.empty(1, dtype=torch.float64, device=dev)
+        check(lib().mppi_weights(self.h, K, H, _ptr(cost), float(lam), _ptr(u_mean), _ptr(u_eps),
+                                 _ptr(w), _ptr(u_new), _ptr(am), _ptr(jm), _stream_handle(stream)),
+              "mppi_weights")
+        return w, u_new, am, jm
+
+
+def run_workload(ctx: Context, wl, precision=FP32C, **want) -> dict:
+    """Upload a workload, run it, synchronise and return numpy outputs."""
+    import torch
+    db = DeviceBatch(wl)
+    out = DeviceOutputs(db, **want)
+    ctx.rollout(wl.params, db, out, precision)
+    torch.cuda.synchronize()
+    return out.to_numpy()
