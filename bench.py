@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--H", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256, help="rollouts timed on the oracle")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -93,6 +95,12 @@ def main():
             ev[1].record(stream)
         ctx.mppi(out.cost, wl.lam, db.u_mean, db.u_eps, stream)
 
+    if args.calibrate_copy_mb > 0:
+        src = torch.empty(args.calibrate_copy_mb << 20, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

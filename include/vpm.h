@@ -55,6 +55,11 @@ extern "C" {
 #define VPM_SHED_TE 1   /* TEV only (Kutta condition at the trailing edge)    */
 #define VPM_SHED_NONE 2 /* no shedding                                        */
 
+/* rollout kernel variant (vpm_set_path) */
+#define VPM_PATH_AUTO 0   /* LDS-resident wake when it fits, else streaming   */
+#define VPM_PATH_LDS 1    /* LDS-resident only (VPM_ECAPACITY if too large)   */
+#define VPM_PATH_STREAM 2 /* wake in a device workspace, tiles through LDS    */
+
 /* compute precision */
 #define VPM_FP32C 0 /* FP32 interactions, compensated sums; FP64 solve        */
 #define VPM_FP64 1  /* FP64 throughout                                        */
@@ -143,6 +148,13 @@ typedef struct vpm_ctx vpm_ctx;
  * table. Returns VPM_EDEVICE if the device is absent or is not gfx950. */
 VPM_API int vpm_create(vpm_ctx **out, int device);
 VPM_API void vpm_destroy(vpm_ctx *ctx);
+
+/* Choose the rollout kernel variant for later calls on this context. Both
+ * compute the same steps; AUTO keeps the wake in LDS when it fits (up to a few
+ * thousand vortices) and otherwise streams it from a context-owned workspace
+ * of (max_wake0 + 2H) x 24 B (FP32) per resident workgroup, grown on demand
+ * and serialised across streams. Returns VPM_EINVAL for an unknown value. */
+VPM_API int vpm_set_path(vpm_ctx *ctx, int path);
 
 /* Message of the calling thread's last error ("" if none). */
 VPM_API const char *vpm_last_error(void);

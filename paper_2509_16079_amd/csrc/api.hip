@@ -108,14 +108,30 @@ VPM_API int vpm_create(vpm_ctx **out, int device) {
   (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device);
   c->max_lds = lds > optin ? lds : optin;
   if (c->max_lds <= 0) c->max_lds = 65536;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(VPM_EDEVICE, "hipEventCreate failed");
+  }
   *out = c;
+  return VPM_OK;
+}
+
+VPM_API int vpm_set_path(vpm_ctx *ctx, int path) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  if (path < VPM_PATH_AUTO || path > VPM_PATH_STREAM)
+    return fail(VPM_EINVAL, "unknown path");
+  ctx->path = path;
   return VPM_OK;
 }
 
 VPM_API void vpm_destroy(vpm_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
   for (auto &kv : ctx->plate_cache) (void)hipFree(kv.second);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
   delete ctx;
 }
 

@@ -1,30 +1,34 @@
-// rollout.hip -- fused VPM-glider rollout kernel for gfx950.
+// rollout.hip -- fused VPM-glider rollout kernels for gfx950.
 //
-// One workgroup (4 waves) owns one rollout for all H steps; the rollout's
-// wake lives in LDS for the whole horizon, so HBM is touched only to read
-// the initial state and controls and to write results. Per step
-// (Sec. III-A/B of the paper):
+// A workgroup owns one rollout for all H steps. Per step (Sec. III-A/B of
+// the paper):
 //
 //   prologue (1 thread)  plate kinematics; disturbance termination (Sec. V)
-//   pass A   (4 waves)   every source = the wake at the start of the step;
-//                        every target = 2 N_b + 1 surface points (Eq. 12),
-//                        the two edge release points, and every wake vortex
-//                        (the wake part of Eq. 16). Sources are split into 4
-//                        contiguous quarters (one per wave); each lane keeps
-//                        T targets in registers and walks its quarter through
-//                        LDS broadcast reads. FP32 mode sums each 64-source
-//                        tile with plain FMAs and folds tiles into a
-//                        (sum, error) pair with TwoSum; the 4 quarters are
-//                        combined in FP64 in fixed order.
-//   solve    (wave 0)    Kelvin sum (FP64 wave reduction), RHS, FP64
-//                        Gamma_S = K^-1 b (Eq. 11) with the plate inverse
-//                        precomputed once per geometry; Bernoulli loads
-//                        (Eqs. 13-15) with an FP64 wave prefix scan;
-//                        elevator and rigid-body accelerations; shedding.
+//   pass A   (all waves) sources = the wake at the start of the step;
+//                        targets = 2 N_b + 1 surface points (Eq. 12), the
+//                        two edge release points and every wake vortex (the
+//                        wake part of Eq. 16). FP32 mode sums 64-source tiles
+//                        with plain FMAs and folds each tile into a
+//                        (sum, error) pair with TwoSum.
+//   solve    (wave 0)    Kelvin sum (FP64), RHS, Gamma_S = K^-1 b (Eq. 11)
+//                        from a plate inverse built once per geometry,
+//                        Bernoulli loads (Eqs. 13-15), elevator and
+//                        rigid-body accelerations, shedding.
 //   pass B   (all)       each wake vortex adds the new LEV/TEV (regularised)
-//                        and bound (singular) terms -- completing Eq. 16 in
-//                        FIFO order -- then Euler advection and decay.
+//                        and bound (singular) terms, completing Eq. 16 in
+//                        FIFO order; Euler advection and decay (Eq. 17).
 //   epilogue (1 thread)  merge the two oldest above N_w,max; glider Euler.
+//
+// Two variants differ only in where the wake lives and how pass A walks it:
+//  - rollout_lds_kernel (4 waves): the wake is resident in LDS for the whole
+//    horizon. Sources are split into 4 contiguous quarters (one per wave);
+//    each lane keeps T targets in registers; the quarters are added in FP64
+//    in fixed order.
+//  - rollout_stream_kernel (NW waves, persistent): the wake lives in a
+//    per-workgroup slot of a global workspace; 1024-source tiles are staged
+//    cooperatively through LDS and every wave walks all of them for its own
+//    targets, so each target sums its sources in strict FIFO order. It
+//    serves wakes too large for LDS (tens of thousands of vortices).
 //
 // The N^2 work is pure VALU: 8 FP32 ops + 1 v_rsq_f32 per regularised pair,
 // no MFMA (the sum is not a dense contraction).
@@ -35,9 +39,8 @@
 namespace vpm {
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
-constexpr int kTile = 64;  // sources per compensation tile
+constexpr int kTile = 64;          // sources per compensation tile
+constexpr int kStreamTile = 1024;  // sources per LDS stage (streaming kernel)
 constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
 constexpr double kTwoPi = 6.28318530717958647692528676655900577;
 
@@ -68,6 +71,7 @@ struct KArgs {
   int64_t *pair_count;
   const int64_t *wake_off;
   int off_vsurf, off_red, off_vel, off_kinv;  // byte offsets into dynamic LDS
+  void *ws_src, *ws_vel;  // streaming workspace: one slot of `cap` per block
 };
 
 // Per-rollout scalars shared by the workgroup.
@@ -94,6 +98,8 @@ __device__ inline float rsq(float d) { return __builtin_amdgcn_rsqf(d); }
 __device__ inline double rsq(double d) { return 1.0 / sqrt(d); }
 __device__ inline float rcp(float d) { return __builtin_amdgcn_rcpf(d); }
 __device__ inline double rcp(double d) { return 1.0 / d; }
+__device__ inline float tiny(float) { return 1.17549435e-38f; }
+__device__ inline double tiny(double) { return 2.2250738585072014e-308; }
 
 // Regularised kernel (Eq. 5) times Gamma, with g = Gamma/(2 pi) folded in:
 // g (-dz, dx) / sqrt(rc^4 + r^4).
@@ -105,12 +111,12 @@ __device__ inline void reg_term(R dx, R dz, R g, R rc4, R &vx, R &vz) {
   vz += dx * k;
 }
 
-// Singular kernel (Eq. 4) times Gamma, g = Gamma/(2 pi): g (-dz, dx) / r^2;
-// a coincident point contributes 0.
+// Singular kernel (Eq. 4) times Gamma, g = Gamma/(2 pi): g (-dz, dx) / r^2.
+// A coincident point has dx = dz = 0 and a finite k, so it contributes 0.
 template <typename R>
 __device__ inline void sing_term(R dx, R dz, R g, R &vx, R &vz) {
   R r2 = dx * dx + dz * dz;
-  R k = r2 > R(0) ? g * rcp(r2) : R(0);
+  R k = g * rcp(fmax(r2, tiny(r2)));
   vx -= dz * k;
   vz += dx * k;
 }
@@ -124,14 +130,31 @@ __device__ inline void two_sum(float &s, float &c, float t) {
   c += err;
 }
 
-// Pass A over one wave's source range for the T targets of each lane.
 template <typename R, int T>
-__device__ void pass_a(const typename SrcOf<R>::type *__restrict__ src, int s_lo,
-                       int s_hi, const R (&tx)[T], const R (&tz)[T], R rc4,
-                       Vec2<R> *__restrict__ red, int lane) {
-  R sx[T], sz[T], cx[T], cz[T];
+__device__ inline void fold_tile(R (&sx)[T], R (&sz)[T], R (&cx)[T], R (&cz)[T],
+                                 const R (&ax)[T], const R (&az)[T]) {
+  if constexpr (sizeof(R) == 4) {
 #pragma unroll
-  for (int j = 0; j < T; ++j) sx[j] = sz[j] = cx[j] = cz[j] = R(0);
+    for (int j = 0; j < T; ++j) {
+      two_sum(sx[j], cx[j], ax[j]);
+      two_sum(sz[j], cz[j], az[j]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      sx[j] += ax[j];
+      sz[j] += az[j];
+    }
+  }
+}
+
+// Sources [s_lo, s_hi) of `src` onto the T targets of this lane, folded
+// every 64 sources.
+template <typename R, int T>
+__device__ inline void accumulate(const typename SrcOf<R>::type *__restrict__ src,
+                                  int s_lo, int s_hi, const R (&tx)[T],
+                                  const R (&tz)[T], R rc4, R (&sx)[T], R (&sz)[T],
+                                  R (&cx)[T], R (&cz)[T]) {
   for (int s0 = s_lo; s0 < s_hi; s0 += kTile) {
     const int s1 = min(s0 + kTile, s_hi);
     R ax[T], az[T];
@@ -143,22 +166,8 @@ __device__ void pass_a(const typename SrcOf<R>::type *__restrict__ src, int s_lo
 #pragma unroll
       for (int j = 0; j < T; ++j) reg_term(tx[j] - v.x, tz[j] - v.z, v.g, rc4, ax[j], az[j]);
     }
-    if constexpr (sizeof(R) == 4) {
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        two_sum(sx[j], cx[j], ax[j]);
-        two_sum(sz[j], cz[j], az[j]);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        sx[j] += ax[j];
-        sz[j] += az[j];
-      }
-    }
+    fold_tile<R, T>(sx, sz, cx, cz, ax, az);
   }
-#pragma unroll
-  for (int j = 0; j < T; ++j) red[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
 }
 
 template <typename R>
@@ -177,30 +186,22 @@ __device__ inline void surface_point(const Shared<R> &sh, int t, int nb, R lb,
   pz = sh.le[1] + s * sh.et[1];
 }
 
-template <typename R, int T>
-__device__ void pass_a_chunk(const KArgs &a, const Shared<R> &sh,
-                             const typename SrcOf<R>::type *src, Vec2<R> *red,
-                             int c0, int NT, int head, int s_lo, int s_hi,
-                             int lane, int wave) {
-  const int nb = a.nb, n_surf = 2 * nb + 3;
-  const R lb = R(a.chord / nb), ds = R(a.shed_frac * a.chord), c = R(a.chord);
-  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
-  R tx[T], tz[T];
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    const int t = c0 + lane + 64 * j;
-    tx[j] = tz[j] = R(0);
-    if (t < NT) {
-      if (t < n_surf) {
-        surface_point(sh, t, nb, lb, ds, c, tx[j], tz[j]);
-      } else {
-        const auto v = src[head + t - n_surf];
-        tx[j] = v.x;
-        tz[j] = v.z;
-      }
-    }
+// Position of pass-A target t: surface points first, then the wake.
+template <typename R>
+__device__ inline void target_pos(const KArgs &a, const Shared<R> &sh,
+                                  const typename SrcOf<R>::type *src, int t,
+                                  int NT, int head, R &px, R &pz) {
+  const int n_surf = 2 * a.nb + 3;
+  px = pz = R(0);
+  if (t >= NT) return;
+  if (t < n_surf) {
+    surface_point(sh, t, a.nb, R(a.chord / a.nb), R(a.shed_frac * a.chord),
+                  R(a.chord), px, pz);
+  } else {
+    const auto v = src[head + t - n_surf];
+    px = v.x;
+    pz = v.z;
   }
-  pass_a<R, T>(src, s_lo, s_hi, tx, tz, rc4, red + wave * 64 * T, lane);
 }
 
 // Segment a-b against the chord rectangle inflated by 2 % of chord opposite
@@ -253,6 +254,7 @@ __device__ void geometry(const KArgs &a, Shared<R> &sh) {
   sh.tev[1] = sh.le[1] + s_tev * sh.et[1];
 }
 
+// Thread 0 at the start of a step: kinematics and termination.
 template <typename R>
 __device__ void prologue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src) {
@@ -268,29 +270,19 @@ __device__ void prologue(const KArgs &a, Shared<R> &sh,
   }
 }
 
-// MINW: waves per SIMD the register budget must allow (4 for FP32 fills a CU
-// with four rollouts; FP64 takes 2 to avoid spills).
-template <typename R, int TMAX, int MINW>
-__global__ __launch_bounds__(kThreads, MINW) void rollout_kernel(KArgs a) {
+// Load rollout k's initial state. Returns false (after writing the failure
+// outputs) when its field is invalid or larger than max_wake0; uniform over
+// the workgroup.
+template <typename R>
+__device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *src,
+                      int k, int tid, int nthr) {
   using Src = typename SrcOf<R>::type;
-  extern __shared__ __align__(32) unsigned char lds[];
-  __shared__ Shared<R> sh;
-  Src *src = reinterpret_cast<Src *>(lds);
-  double2 *vsurf = reinterpret_cast<double2 *>(lds + a.off_vsurf);
-  Vec2<R> *red = reinterpret_cast<Vec2<R> *>(lds + a.off_red);
-  Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(lds + a.off_vel);
-  double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
-
-  const int k = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nb = a.nb, S = a.S, nc = nb + 1, n_surf = 2 * nb + 3;
-  const double dt = a.dt, lb = a.chord / nb;
-
+  const int nb = a.nb;
   const int fo = a.field_of ? a.field_of[k] : k;
   const bool bad_field = fo < 0 || fo >= a.n_fields;
   const int64_t f0 = bad_field ? 0 : a.field_off[fo];
   const int n0 = bad_field ? -1 : static_cast<int>(a.field_off[fo + 1] - f0);
-  if (n0 < 0 || n0 > a.max_wake0) {  // uniform over the workgroup
+  if (n0 < 0 || n0 > a.max_wake0) {
     if (tid < 7) a.g_final[7 * k + tid] = a.g0[7 * k + tid];
     if (tid == 0) {
       a.cost[k] = INFINITY;
@@ -299,12 +291,10 @@ __global__ __launch_bounds__(kThreads, MINW) void rollout_kernel(KArgs a) {
       if (a.n_final) a.n_final[k] = 0;
       if (a.n_vel_last) a.n_vel_last[k] = 0;
     }
-    return;
+    return false;
   }
-
-  for (int q = tid; q < n0; q += kThreads)
+  for (int q = tid; q < n0; q += nthr)
     src[q] = Src{R(a.wx[f0 + q]), R(a.wz[f0 + q]), R(a.wg[f0 + q] * kInv2Pi), R(0)};
-  for (int q = tid; q < S * S; q += kThreads) kinv[q] = a.kinv_t[q];
   if (tid < 7) {
     sh.g[tid] = R(a.g0[7 * k + tid]);
     if (a.traj) a.traj[(size_t)k * (a.H + 1) * 7 + tid] = a.g0[7 * k + tid];
@@ -326,214 +316,189 @@ __global__ __launch_bounds__(kThreads, MINW) void rollout_kernel(KArgs a) {
       sh.pb[q] = pb;
     }
   }
-  __syncthreads();
+  return true;
+}
 
-  const R one_decay = R(1.0 - a.decay * dt);
+// Wave 0: Kelvin sum, surface solve, loads, dynamics, shedding.
+template <typename R>
+__device__ __forceinline__ void solve_section(
+    const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *src, Vec2<R> *vel,
+    const double2 *vsurf, const double *kinv, int k, int n, int head, int n_w,
+    int lane) {
+  using Src = typename SrcOf<R>::type;
+  const int nb = a.nb, S = a.S, nc = nb + 1;
+  const double dt = a.dt, lb = a.chord / nb;
   const R dtr = R(dt);
-  for (int n = 0; n < a.H; ++n) {
-    // ---- prologue (thread 0): kinematics and disturbance termination; for
-    // n > 0 it follows the previous step's epilogue in the same section
-    if (n == 0) {
-      if (tid == 0) prologue(a, sh, src);
-      __syncthreads();
-    }
-    const int head = sh.head, n_w = sh.n_w;
-    const int NT = n_surf + n_w;
-
-    // ---- pass A: wake sources onto surface, release and wake targets
-    const int s_lo = head + (n_w * wave) / kWaves;
-    const int s_hi = head + (n_w * (wave + 1)) / kWaves;
-    for (int c0 = 0; c0 < NT;) {
-      const int rem = NT - c0;
-      int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
-      while (T > 1 && 64 * T > rem) T >>= 1;
-      switch (T) {
-        case 1: pass_a_chunk<R, 1>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-        case 2: if constexpr (TMAX >= 2) pass_a_chunk<R, 2>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-        case 4: if constexpr (TMAX >= 4) pass_a_chunk<R, 4>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-        default: if constexpr (TMAX >= 8) pass_a_chunk<R, 8>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-      }
-      __syncthreads();
-      const int span = 64 * T;
-      for (int t = tid; t < span && c0 + t < NT; t += kThreads) {
-        double vx = 0.0, vz = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-          const Vec2<R> r = red[w * span + t];
-          vx += double(r.x);
-          vz += double(r.z);
-        }
-        const int tt = c0 + t;
-        if (tt < n_surf)
-          vsurf[tt] = make_double2(vx, vz);
-        else
-          vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};
-      }
-      __syncthreads();
-      c0 += span;
-    }
-
-    // ---- wave 0: Kelvin sum, surface solve, loads, dynamics, shedding
-    if (wave == 0) {
-      double sg = 0.0;
-      for (int q = lane; q < n_w; q += 64) sg += double(src[head + q].g);
-      const double sum_gw = kTwoPi * wave_sum(sg);
-      const double lex = sh.le[0], lez = sh.le[1], etx = sh.et[0], etz = sh.et[1];
-      const double enx = sh.en[0], enz = sh.en[1];
-      const double xwx = sh.xw[0], xwz = sh.xw[1], thd = sh.g[6];
-      const double xwdx = sh.xwd[0], xwdz = sh.xwd[1];
-      // b_i = -v~(r_ci).n with v~ = v_W - xw_dot - thd J(r - x_w) (Eq. 12)
-      auto rhs = [&](int r) -> double {
-        if (r >= S) return 0.0;
-        if (r == S - 1) return -sum_gw;
-        const double px = lex + r * lb * etx, pz = lez + r * lb * etz;
-        const double2 vw = vsurf[r];
-        const double vx = vw.x - xwdx + thd * (pz - xwz);
-        const double vz = vw.y - xwdz - thd * (px - xwx);
-        return -(vx * enx + vz * enz);
-      };
-      if (lane < S) sh.bvec[lane] = rhs(lane);
-      if (lane + 64 < S) sh.bvec[lane + 64] = rhs(lane + 64);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // Gamma_S = K^-1 b (Eq. 11): lane i owns rows i and i + 64
-      double gam0 = 0.0, gam1 = 0.0;
-      const int i0 = lane < S ? lane : 0, i1 = lane + 64 < S ? lane + 64 : 0;
+  double sg = 0.0;
+  for (int q = lane; q < n_w; q += 64) sg += double(src[head + q].g);
+  const double sum_gw = kTwoPi * wave_sum(sg);
+  const double lex = sh.le[0], lez = sh.le[1], etx = sh.et[0], etz = sh.et[1];
+  const double enx = sh.en[0], enz = sh.en[1];
+  const double xwx = sh.xw[0], xwz = sh.xw[1], thd = sh.g[6];
+  const double xwdx = sh.xwd[0], xwdz = sh.xwd[1];
+  // b_i = -v~(r_ci).n with v~ = v_W - xw_dot - thd J(r - x_w) (Eq. 12)
+  auto rhs = [&](int r) -> double {
+    if (r >= S) return 0.0;
+    if (r == S - 1) return -sum_gw;
+    const double px = lex + r * lb * etx, pz = lez + r * lb * etz;
+    const double2 vw = vsurf[r];
+    const double vx = vw.x - xwdx + thd * (pz - xwz);
+    const double vz = vw.y - xwdz - thd * (px - xwx);
+    return -(vx * enx + vz * enz);
+  };
+  if (lane < S) sh.bvec[lane] = rhs(lane);
+  if (lane + 64 < S) sh.bvec[lane + 64] = rhs(lane + 64);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // Gamma_S = K^-1 b (Eq. 11): lane i owns rows i and i + 64
+  double gam0 = 0.0, gam1 = 0.0;
+  const int i0 = lane < S ? lane : 0, i1 = lane + 64 < S ? lane + 64 : 0;
 #pragma unroll 8
-      for (int j = 0; j < S; ++j) {
-        const double bj = sh.bvec[j];
-        gam0 += kinv[j * S + i0] * bj;
-        gam1 += kinv[j * S + i1] * bj;
-      }
-      auto row = [&](int r) -> double {
-        return r < 64 ? __shfl(gam0, r, 64) : __shfl(gam1, r - 64, 64);
-      };
-      const double glev = row(nb), gtev = row(nb + 1);
-      if (a.gamma_s) {
-        double *gs = a.gamma_s + ((size_t)k * a.H + n) * S;
-        if (lane < S) gs[lane] = gam0;
-        if (lane + 64 < S) gs[lane + 64] = gam1;
-      }
-      // Eqs. 13-15. With P_j the prefix sums of Gamma_b, the force needs
-      // sum_j (P_j - P'_j) = sum_k (N_b - k) dGamma_k and the moment
-      // sum_j arm_j (P_j - P'_j) = sum_k A_k dGamma_k, A_k = sum_{j>=k} arm_j
-      // = -(N_b - k) k l_b / 2 (arm_j = c/2 - (j + 1/2) l_b): two plain sums.
-      const bool on = lane < nb;
-      const double gbj = on ? gam0 : 0.0;
-      const double dgb = on ? gam0 - sh.gb_prev[lane] : 0.0;
-      const double sj = (lane + 0.5) * lb;
-      const double bx = lex + sj * etx, bz = lez + sj * etz;
-      const double2 vb = on ? vsurf[nc + lane] : make_double2(0.0, 0.0);
-      const double vtx = vb.x - xwdx + thd * (bz - xwz);
-      const double vtz = vb.y - xwdz - thd * (bx - xwx);
-      const double qt = vtx * etx + vtz * etz;
-      const double arm = 0.5 * a.chord - sj;
-      const double local = (gbj / lb) * qt + glev / dt;
-      const double tf = on ? local + (nb - lane) * dgb / dt : 0.0;
-      const double tm = on ? arm * local - 0.5 * (nb - lane) * lane * lb * dgb / dt : 0.0;
-      const double sdp = a.rho * wave_sum(tf);
-      const double sarm = a.rho * wave_sum(tm);
-      if (on) {
-        sh.gb_prev[lane] = gbj;
-        sh.bpos[lane][0] = R(bx);
-        sh.bpos[lane][1] = R(bz);
-        sh.bgam[lane] = R(gbj * kInv2Pi);
-      }
-      if (lane == 0) {
-        const double fwx = lb * a.span * sdp * enx, fwz = lb * a.span * sdp * enz;
-        const double mw = lb * a.span * sarm;
-        // Sec. III-B: elevator force and rigid-body accelerations
-        const R x = sh.g[0], z = sh.g[1], th = sh.g[2], ph = sh.g[3];
-        const R xd = sh.g[4], zd = sh.g[5], thr = sh.g[6];
-        const R u = R(a.u_mean[n] + a.u_eps[(size_t)k * a.H + n]);
-        const R l = R(a.l_body), le = R(a.l_elev);
-        const R ct = cos(th), st = sin(th), ctp = cos(th + ph), stp = sin(th + ph);
-        const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
-        const R xed = xd + l * thr * st + le * (thr + u) * stp;
-        const R zed = zd - l * thr * ct - le * (thr + u) * ctp;
-        const R alpha = th + ph - atan2(zed, xed);
-        const R fe = R(0.5 * a.rho * a.s_elev) * (xed * xed + zed * zed) * R(2) * sin(alpha);
-        const R fex = -fe * stp, fez = fe * ctp;
-        const R fx = R(fwx) + fex, fz = R(fwz) + fez;
-        const R ax_ = fx / R(a.mass);
-        const R az_ = fz / R(a.mass) - R(a.grav);
-        const R mom = (sh.xw[0] - x) * R(fwz) - (sh.xw[1] - z) * R(fwx) +
-                      (xe - x) * fez - (ze - z) * fex + R(mw);
-        const R ath = mom / R(a.inertia);
-        sh.gn[0] = x + dtr * xd;
-        sh.gn[1] = z + dtr * zd;
-        sh.gn[2] = th + dtr * thr;
-        sh.gn[3] = ph + dtr * u;
-        sh.gn[4] = xd + dtr * ax_;
-        sh.gn[5] = zd + dtr * az_;
-        sh.gn[6] = thr + dtr * ath;
-        // shedding: LEV then TEV join the wake tail (Sec. III-A)
-        const int p = head + n_w;
-        sh.shed_g[0] = R(glev * kInv2Pi);
-        sh.shed_g[1] = R(gtev * kInv2Pi);
-        src[p] = Src{sh.lev[0], sh.lev[1], sh.shed_g[0], R(0)};
-        src[p + 1] = Src{sh.tev[0], sh.tev[1], sh.shed_g[1], R(0)};
-        const double2 vl = vsurf[2 * nb + 1], vt = vsurf[2 * nb + 2];
-        vel[p] = Vec2<R>{R(vl.x), R(vl.y)};
-        vel[p + 1] = Vec2<R>{R(vt.x), R(vt.y)};
-      }
-    }
-    __syncthreads();
-
-    // ---- pass B: edge and bound terms (FIFO order), then advect and decay
-    const int m = n_w + 2;
-    const bool last = (n == a.H - 1);
-    const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
-    for (int t = tid; t < m; t += kThreads) {
-      const int p = head + t;
-      Src s = src[p];
-      const Vec2<R> v0 = vel[p];
-      R ex = R(0), ez = R(0);
-      reg_term(s.x - sh.lev[0], s.z - sh.lev[1], sh.shed_g[0], rc4, ex, ez);
-      reg_term(s.x - sh.tev[0], s.z - sh.tev[1], sh.shed_g[1], rc4, ex, ez);
-      for (int j = 0; j < nb; ++j)
-        sing_term(s.x - sh.bpos[j][0], s.z - sh.bpos[j][1], sh.bgam[j], ex, ez);
-      const double vx = double(v0.x) + double(ex), vz = double(v0.z) + double(ez);
-      if (last && a.vel_last) {
-        double *o = a.vel_last + 2 * (a.wake_off[k] + t);
-        o[0] = vx;
-        o[1] = vz;
-      }
-      s.x = s.x + dtr * R(vx);
-      s.z = s.z + dtr * R(vz);
-      s.g = s.g * one_decay;
-      src[p] = s;
-    }
-    __syncthreads();
-
-    // ---- epilogue: merging and the glider step
-    if (tid == 0) {
-      sh.pairs += (long long)n_w * (2 * nb + 1) + (long long)m * (m - 1) +
-                  (long long)m * nb;
-      int h = sh.head, cnt = m;
-      while (a.n_wake_max > 0 && cnt > a.n_wake_max && cnt >= 2) {
-        const Src s0 = src[h], s1 = src[h + 1];
-        src[h + 1] = Src{R(0.5) * (s0.x + s1.x), R(0.5) * (s0.z + s1.z), s0.g + s1.g, R(0)};
-        for (int q = 0; q < kMaxPairs; ++q)
-          if (sh.pa[q] == h || sh.pa[q] == h + 1 || sh.pb[q] == h || sh.pb[q] == h + 1)
-            sh.pa[q] = sh.pb[q] = -1;
-        ++h;
-        --cnt;
-      }
-      sh.head = h;
-      sh.n_w = cnt;
-      for (int i = 0; i < 7; ++i) sh.g[i] = sh.gn[i];
-      if (a.traj)
-        for (int i = 0; i < 7; ++i)
-          a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
-      if (last && a.n_vel_last) a.n_vel_last[k] = m;
-      if (!last) prologue(a, sh, src);
-    }
-    __syncthreads();
+  for (int j = 0; j < S; ++j) {
+    const double bj = sh.bvec[j];
+    gam0 += kinv[j * S + i0] * bj;
+    gam1 += kinv[j * S + i1] * bj;
   }
+  auto row = [&](int r) -> double {
+    return r < 64 ? __shfl(gam0, r, 64) : __shfl(gam1, r - 64, 64);
+  };
+  const double glev = row(nb), gtev = row(nb + 1);
+  if (a.gamma_s) {
+    double *gs = a.gamma_s + ((size_t)k * a.H + n) * S;
+    if (lane < S) gs[lane] = gam0;
+    if (lane + 64 < S) gs[lane + 64] = gam1;
+  }
+  // Eqs. 13-15. With P_j the prefix sums of Gamma_b, the force needs
+  // sum_j (P_j - P'_j) = sum_k (N_b - k) dGamma_k and the moment
+  // sum_j arm_j (P_j - P'_j) = sum_k A_k dGamma_k, A_k = sum_{j>=k} arm_j
+  // = -(N_b - k) k l_b / 2 (arm_j = c/2 - (j + 1/2) l_b): two plain sums.
+  const bool on = lane < nb;
+  const double gbj = on ? gam0 : 0.0;
+  const double dgb = on ? gam0 - sh.gb_prev[lane] : 0.0;
+  const double sj = (lane + 0.5) * lb;
+  const double bx = lex + sj * etx, bz = lez + sj * etz;
+  const double2 vb = on ? vsurf[nc + lane] : make_double2(0.0, 0.0);
+  const double vtx = vb.x - xwdx + thd * (bz - xwz);
+  const double vtz = vb.y - xwdz - thd * (bx - xwx);
+  const double qt = vtx * etx + vtz * etz;
+  const double arm = 0.5 * a.chord - sj;
+  const double local = (gbj / lb) * qt + glev / dt;
+  const double tf = on ? local + (nb - lane) * dgb / dt : 0.0;
+  const double tm = on ? arm * local - 0.5 * (nb - lane) * lane * lb * dgb / dt : 0.0;
+  const double sdp = a.rho * wave_sum(tf);
+  const double sarm = a.rho * wave_sum(tm);
+  if (on) {
+    sh.gb_prev[lane] = gbj;
+    sh.bpos[lane][0] = R(bx);
+    sh.bpos[lane][1] = R(bz);
+    sh.bgam[lane] = R(gbj * kInv2Pi);
+  }
+  if (lane == 0) {
+    const double fwx = lb * a.span * sdp * enx, fwz = lb * a.span * sdp * enz;
+    const double mw = lb * a.span * sarm;
+    // Sec. III-B: elevator force and rigid-body accelerations
+    const R x = sh.g[0], z = sh.g[1], th = sh.g[2], ph = sh.g[3];
+    const R xd = sh.g[4], zd = sh.g[5], thr = sh.g[6];
+    const R u = R(a.u_mean[n] + a.u_eps[(size_t)k * a.H + n]);
+    const R l = R(a.l_body), le = R(a.l_elev);
+    const R ct = cos(th), st = sin(th), ctp = cos(th + ph), stp = sin(th + ph);
+    const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
+    const R xed = xd + l * thr * st + le * (thr + u) * stp;
+    const R zed = zd - l * thr * ct - le * (thr + u) * ctp;
+    const R alpha = th + ph - atan2(zed, xed);
+    const R fe = R(0.5 * a.rho * a.s_elev) * (xed * xed + zed * zed) * R(2) * sin(alpha);
+    const R fex = -fe * stp, fez = fe * ctp;
+    const R fx = R(fwx) + fex, fz = R(fwz) + fez;
+    const R ax_ = fx / R(a.mass);
+    const R az_ = fz / R(a.mass) - R(a.grav);
+    const R mom = (sh.xw[0] - x) * R(fwz) - (sh.xw[1] - z) * R(fwx) +
+                  (xe - x) * fez - (ze - z) * fex + R(mw);
+    const R ath = mom / R(a.inertia);
+    sh.gn[0] = x + dtr * xd;
+    sh.gn[1] = z + dtr * zd;
+    sh.gn[2] = th + dtr * thr;
+    sh.gn[3] = ph + dtr * u;
+    sh.gn[4] = xd + dtr * ax_;
+    sh.gn[5] = zd + dtr * az_;
+    sh.gn[6] = thr + dtr * ath;
+    // shedding: LEV then TEV join the wake tail (Sec. III-A)
+    const int p = head + n_w;
+    sh.shed_g[0] = R(glev * kInv2Pi);
+    sh.shed_g[1] = R(gtev * kInv2Pi);
+    src[p] = Src{sh.lev[0], sh.lev[1], sh.shed_g[0], R(0)};
+    src[p + 1] = Src{sh.tev[0], sh.tev[1], sh.shed_g[1], R(0)};
+    const double2 vl = vsurf[2 * nb + 1], vt = vsurf[2 * nb + 2];
+    vel[p] = Vec2<R>{R(vl.x), R(vl.y)};
+    vel[p + 1] = Vec2<R>{R(vt.x), R(vt.y)};
+  }
+}
 
-  // ---- outputs
+// All threads: edge and bound terms (FIFO order), then advect and decay.
+template <typename R>
+__device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
+                                       typename SrcOf<R>::type *src,
+                                       const Vec2<R> *vel, int k, bool last,
+                                       int head, int m, int tid, int nthr) {
+  using Src = typename SrcOf<R>::type;
+  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  const R one_decay = R(1.0 - a.decay * a.dt), dtr = R(a.dt);
+  for (int t = tid; t < m; t += nthr) {
+    const int p = head + t;
+    Src s = src[p];
+    const Vec2<R> v0 = vel[p];
+    R ex = R(0), ez = R(0);
+    reg_term(s.x - sh.lev[0], s.z - sh.lev[1], sh.shed_g[0], rc4, ex, ez);
+    reg_term(s.x - sh.tev[0], s.z - sh.tev[1], sh.shed_g[1], rc4, ex, ez);
+    for (int j = 0; j < a.nb; ++j)
+      sing_term(s.x - sh.bpos[j][0], s.z - sh.bpos[j][1], sh.bgam[j], ex, ez);
+    const double vx = double(v0.x) + double(ex), vz = double(v0.z) + double(ez);
+    if (last && a.vel_last) {
+      double *o = a.vel_last + 2 * (a.wake_off[k] + t);
+      o[0] = vx;
+      o[1] = vz;
+    }
+    s.x = s.x + dtr * R(vx);
+    s.z = s.z + dtr * R(vz);
+    s.g = s.g * one_decay;
+    src[p] = s;
+  }
+}
+
+// Thread 0 at the end of a step: merging and the glider step; then, unless
+// it is the last step, the next step's prologue.
+template <typename R>
+__device__ void epilogue(const KArgs &a, Shared<R> &sh,
+                         typename SrcOf<R>::type *src, int k, int n, int n_w) {
+  using Src = typename SrcOf<R>::type;
+  const int nb = a.nb, m = n_w + 2;
+  const bool last = (n == a.H - 1);
+  sh.pairs += (long long)n_w * (2 * nb + 1) + (long long)m * (m - 1) + (long long)m * nb;
+  int h = sh.head, cnt = m;
+  while (a.n_wake_max > 0 && cnt > a.n_wake_max && cnt >= 2) {
+    const Src s0 = src[h], s1 = src[h + 1];
+    src[h + 1] = Src{R(0.5) * (s0.x + s1.x), R(0.5) * (s0.z + s1.z), s0.g + s1.g, R(0)};
+    for (int q = 0; q < kMaxPairs; ++q)
+      if (sh.pa[q] == h || sh.pa[q] == h + 1 || sh.pb[q] == h || sh.pb[q] == h + 1)
+        sh.pa[q] = sh.pb[q] = -1;
+    ++h;
+    --cnt;
+  }
+  sh.head = h;
+  sh.n_w = cnt;
+  for (int i = 0; i < 7; ++i) sh.g[i] = sh.gn[i];
+  if (a.traj)
+    for (int i = 0; i < 7; ++i)
+      a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
+  if (last && a.n_vel_last) a.n_vel_last[k] = m;
+  if (!last) prologue(a, sh, src);
+}
+
+// Final outputs of rollout k.
+template <typename R>
+__device__ void finish(const KArgs &a, const Shared<R> &sh,
+                       const typename SrcOf<R>::type *src, int k, int tid,
+                       int nthr) {
   if (tid == 0) {
     bool finite = true;
     double j = 0.0;
@@ -553,14 +518,198 @@ __global__ __launch_bounds__(kThreads, MINW) void rollout_kernel(KArgs a) {
     const int64_t o = a.wake_off[k];
     const int capo = static_cast<int>(a.wake_off[k + 1] - o);
     const int cnt = min(sh.n_w, capo);
-    for (int t = tid; t < cnt; t += kThreads) {
-      const Src s = src[sh.head + t];
+    for (int t = tid; t < cnt; t += nthr) {
+      const auto s = src[sh.head + t];
       if (a.wx_out) a.wx_out[o + t] = double(s.x);
       if (a.wz_out) a.wz_out[o + t] = double(s.z);
       if (a.wg_out) a.wg_out[o + t] = double(s.g) * kTwoPi;
     }
   }
 }
+
+// ---------------------------------------------------------------- LDS path
+
+constexpr int kLdsWaves = 4;
+constexpr int kLdsThreads = 64 * kLdsWaves;
+
+template <typename R, int T>
+__device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
+                                 const typename SrcOf<R>::type *src, Vec2<R> *red,
+                                 int c0, int NT, int head, int s_lo, int s_hi,
+                                 int lane, int wave) {
+  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  R tx[T], tz[T], sx[T], sz[T], cx[T], cz[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    target_pos(a, sh, src, c0 + lane + 64 * j, NT, head, tx[j], tz[j]);
+    sx[j] = sz[j] = cx[j] = cz[j] = R(0);
+  }
+  accumulate<R, T>(src, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
+  Vec2<R> *out = red + wave * 64 * T;
+#pragma unroll
+  for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
+}
+
+// MINW: waves per SIMD the register budget must allow (4 for FP32 fills a CU
+// with four rollouts; FP64 takes 2 to avoid spills).
+template <typename R, int TMAX, int MINW>
+__global__ __launch_bounds__(kLdsThreads, MINW) void rollout_lds_kernel(KArgs a) {
+  using Src = typename SrcOf<R>::type;
+  extern __shared__ __align__(32) unsigned char lds[];
+  __shared__ Shared<R> sh;
+  Src *src = reinterpret_cast<Src *>(lds);
+  double2 *vsurf = reinterpret_cast<double2 *>(lds + a.off_vsurf);
+  Vec2<R> *red = reinterpret_cast<Vec2<R> *>(lds + a.off_red);
+  Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(lds + a.off_vel);
+  double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
+
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n_surf = 2 * a.nb + 3;
+  if (!setup(a, sh, src, k, tid, kLdsThreads)) return;
+  for (int q = tid; q < a.S * a.S; q += kLdsThreads) kinv[q] = a.kinv_t[q];
+  __syncthreads();
+
+  for (int n = 0; n < a.H; ++n) {
+    if (n == 0) {
+      if (tid == 0) prologue(a, sh, src);
+      __syncthreads();
+    }
+    const int head = sh.head, n_w = sh.n_w;
+    const int NT = n_surf + n_w;
+
+    // pass A: each wave takes a contiguous quarter of the sources
+    const int s_lo = head + (n_w * wave) / kLdsWaves;
+    const int s_hi = head + (n_w * (wave + 1)) / kLdsWaves;
+    for (int c0 = 0; c0 < NT;) {
+      const int rem = NT - c0;
+      int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
+      while (T > 1 && 64 * T > rem) T >>= 1;
+      switch (T) {
+        case 1: lds_pass_a_chunk<R, 1>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+        case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+        default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+      }
+      __syncthreads();
+      const int span = 64 * T;
+      for (int t = tid; t < span && c0 + t < NT; t += kLdsThreads) {
+        double vx = 0.0, vz = 0.0;
+#pragma unroll
+        for (int w = 0; w < kLdsWaves; ++w) {
+          const Vec2<R> r = red[w * span + t];
+          vx += double(r.x);
+          vz += double(r.z);
+        }
+        const int tt = c0 + t;
+        if (tt < n_surf)
+          vsurf[tt] = make_double2(vx, vz);
+        else
+          vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};
+      }
+      __syncthreads();
+      c0 += span;
+    }
+
+    if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
+    __syncthreads();
+    pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kLdsThreads);
+    __syncthreads();
+    if (tid == 0) epilogue(a, sh, src, k, n, n_w);
+    __syncthreads();
+  }
+  finish(a, sh, src, k, tid, kLdsThreads);
+}
+
+// ---------------------------------------------------------- streaming path
+
+template <typename R, int T, int NW>
+__device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
+                                    const typename SrcOf<R>::type *src,
+                                    typename SrcOf<R>::type *tile, Vec2<R> *vel,
+                                    double2 *vsurf, int c0, int NT, int head,
+                                    int n_w, int tid, int lane, int wave) {
+  const int n_surf = 2 * a.nb + 3;
+  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  R tx[T], tz[T], sx[T], sz[T], cx[T], cz[T];
+  const int t0 = c0 + wave * 64 + lane;  // target j of this lane: t0 + j 64 NW
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    target_pos(a, sh, src, t0 + j * 64 * NW, NT, head, tx[j], tz[j]);
+    sx[j] = sz[j] = cx[j] = cz[j] = R(0);
+  }
+  for (int s0 = 0; s0 < n_w; s0 += kStreamTile) {
+    const int cnt = min(kStreamTile, n_w - s0);
+    for (int q = tid; q < cnt; q += 64 * NW) tile[q] = src[head + s0 + q];
+    __syncthreads();
+    accumulate<R, T>(tile, 0, cnt, tx, tz, rc4, sx, sz, cx, cz);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int t = t0 + j * 64 * NW;
+    if (t >= NT) continue;
+    const double vx = double(sx[j]) + double(cx[j]), vz = double(sz[j]) + double(cz[j]);
+    if (t < n_surf)
+      vsurf[t] = make_double2(vx, vz);
+    else
+      vel[head + t - n_surf] = Vec2<R>{R(vx), R(vz)};
+  }
+}
+
+// Persistent: workgroup b runs rollouts b, b + G, b + 2G, ... with its wake in
+// workspace slot b (a.cap entries of sources and of velocities).
+template <typename R, int TMAX, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a) {
+  using Src = typename SrcOf<R>::type;
+  constexpr int kThr = 64 * NW;
+  extern __shared__ __align__(32) unsigned char lds[];
+  __shared__ Shared<R> sh;
+  Src *tile = reinterpret_cast<Src *>(lds);
+  double2 *vsurf = reinterpret_cast<double2 *>(lds + a.off_vsurf);
+  double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
+  Src *src = reinterpret_cast<Src *>(a.ws_src) + (size_t)blockIdx.x * a.cap;
+  Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(a.ws_vel) + (size_t)blockIdx.x * a.cap;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n_surf = 2 * a.nb + 3;
+  for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
+
+  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+    __syncthreads();
+    if (!setup(a, sh, src, k, tid, kThr)) continue;
+    __syncthreads();
+    for (int n = 0; n < a.H; ++n) {
+      if (n == 0) {
+        if (tid == 0) prologue(a, sh, src);
+        __syncthreads();
+      }
+      const int head = sh.head, n_w = sh.n_w;
+      const int NT = n_surf + n_w;
+      // pass A in rounds of 64 * NW * T targets (T shrinks for the tail)
+      for (int c0 = 0; c0 < NT;) {
+        const int rem = NT - c0;
+        int T = TMAX;
+        while (T > 1 && 64 * NW * T > rem) T >>= 1;
+        switch (T) {
+          case 1: stream_pass_a_round<R, 1, NW>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+        }
+        c0 += 64 * NW * T;
+      }
+      __syncthreads();
+      if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
+      __syncthreads();
+      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr);
+      __syncthreads();
+      if (tid == 0) epilogue(a, sh, src, k, n, n_w);
+      __syncthreads();
+    }
+    finish(a, sh, src, k, tid, kThr);
+  }
+}
+
+// ------------------------------------------------------------------ host
 
 template <typename R>
 int lds_layout(int cap, int nb, int tmax, KArgs &a) {
@@ -572,28 +721,85 @@ int lds_layout(int cap, int nb, int tmax, KArgs &a) {
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = static_cast<int>(off);
-  off += (size_t)kWaves * 64 * tmax * sizeof(Vec2<R>);
+  off += (size_t)kLdsWaves * 64 * tmax * sizeof(Vec2<R>);
   a.off_vel = static_cast<int>(off);
   off += (size_t)cap * sizeof(Vec2<R>);
   return static_cast<int>(off);
 }
 
-template <typename R, int TMAX, int MINW>
-int launch_t(vpm_ctx *ctx, KArgs &a, hipStream_t stream) {
-  const int lds = lds_layout<R>(a.cap, a.nb, TMAX, a);
-  const int static_lds = static_cast<int>(sizeof(Shared<R>));
-  if (lds + static_lds > ctx->max_lds)
-    return fail(VPM_ECAPACITY,
-                "wake capacity " + std::to_string(a.cap) + " needs " +
-                    std::to_string(lds + static_lds) + " B of LDS, limit " +
-                    std::to_string(ctx->max_lds));
-  auto kern = rollout_kernel<R, TMAX, MINW>;
-  if (lds > 65536)
+template <typename R>
+int stream_layout(int nb, KArgs &a) {
+  size_t off = (size_t)kStreamTile * sizeof(typename SrcOf<R>::type);
+  a.off_kinv = static_cast<int>(off);
+  off += (size_t)a.S * a.S * sizeof(double);
+  a.off_vsurf = static_cast<int>(off);
+  off += (size_t)(2 * nb + 3) * sizeof(double2);
+  a.off_red = a.off_vel = 0;
+  return static_cast<int>(off);
+}
+
+template <typename Kern>
+int set_lds(Kern kern, int bytes) {
+  if (bytes > 65536)
     VPM_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    lds));
-  hipLaunchKernelGGL(kern, dim3(a.K), dim3(kThreads), lds, stream, a);
+                                    bytes));
+  return VPM_OK;
+}
+
+template <typename R, int TMAX, int MINW>
+int launch_lds(vpm_ctx *ctx, KArgs &a, hipStream_t stream, bool *fits) {
+  const int lds = lds_layout<R>(a.cap, a.nb, TMAX, a);
+  *fits = lds + static_cast<int>(sizeof(Shared<R>)) <= ctx->max_lds;
+  if (!*fits) return VPM_OK;
+  auto kern = rollout_lds_kernel<R, TMAX, MINW>;
+  int rc = set_lds(kern, lds);
+  if (rc != VPM_OK) return rc;
+  hipLaunchKernelGGL(kern, dim3(a.K), dim3(kLdsThreads), lds, stream, a);
   VPM_HIP_TRY(hipGetLastError());
+  return VPM_OK;
+}
+
+// Grow the context's streaming workspace to `bytes` (device-synchronises
+// before freeing a smaller one).
+int ensure_workspace(vpm_ctx *ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return VPM_OK;
+  if (ctx->ws) {
+    VPM_HIP_TRY(hipDeviceSynchronize());
+    VPM_HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(VPM_ENOMEM, "hipMalloc of the streaming workspace failed");
+  }
+  ctx->ws_bytes = bytes;
+  return VPM_OK;
+}
+
+template <typename R, int TMAX, int NW>
+int launch_stream(vpm_ctx *ctx, KArgs &a, hipStream_t stream) {
+  const int lds = stream_layout<R>(a.nb, a);
+  if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
+    return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
+  auto kern = rollout_stream_kernel<R, TMAX, NW>;
+  int rc = set_lds(kern, lds);
+  if (rc != VPM_OK) return rc;
+  const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
+  const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
+  std::lock_guard<std::mutex> lock(ctx->ws_mu);
+  rc = ensure_workspace(ctx, slot * grid);
+  if (rc != VPM_OK) return rc;
+  // calls that share the workspace are ordered across streams
+  if (ctx->ws_event_valid) VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
+  a.ws_src = ctx->ws;
+  a.ws_vel = static_cast<char *>(ctx->ws) +
+             (size_t)grid * a.cap * sizeof(typename SrcOf<R>::type);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a);
+  VPM_HIP_TRY(hipGetLastError());
+  VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
+  ctx->ws_event_valid = true;
   return VPM_OK;
 }
 
@@ -655,8 +861,19 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.wg_out = wake ? out->wg : nullptr;
   a.vel_last = wake ? out->vel_last : nullptr;
   a.n_vel_last = out->n_vel_last;
-  if (p->precision == VPM_FP64) return launch_t<double, 2, 2>(ctx, a, stream);
-  return launch_t<float, 4, 4>(ctx, a, stream);
+  const bool fp64 = p->precision == VPM_FP64;
+  const int path = ctx->path;
+  if (path != VPM_PATH_STREAM) {
+    bool fits = false;
+    const int rc = fp64 ? launch_lds<double, 2, 2>(ctx, a, stream, &fits)
+                        : launch_lds<float, 4, 4>(ctx, a, stream, &fits);
+    if (rc != VPM_OK || fits) return rc;
+    if (path == VPM_PATH_LDS)
+      return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(a.cap) +
+                                     " does not fit the LDS-resident kernel");
+  }
+  return fp64 ? launch_stream<double, 2, 8>(ctx, a, stream)
+              : launch_stream<float, 4, 16>(ctx, a, stream);
 }
 
 }  // namespace vpm

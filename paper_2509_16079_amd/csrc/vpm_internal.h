@@ -58,8 +58,16 @@ struct vpm_ctx {
   int device = 0;
   int max_lds = 65536;      // dynamic LDS bytes one workgroup may use
   int n_cu = 0;
+  int path = VPM_PATH_AUTO; // kernel variant selection (vpm_set_path)
   std::mutex mu;
   std::map<vpm::PlateKey, double *> plate_cache;  // device inverses
+  // streaming-kernel workspace, shared by calls on this context; each launch
+  // that uses it waits for the previous one (ws_event) whatever the stream
+  std::mutex ws_mu;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipEvent_t ws_event = nullptr;
+  bool ws_event_valid = false;
 };
 
 namespace vpm {

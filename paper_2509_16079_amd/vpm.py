@@ -20,6 +20,7 @@ EINVAL, ENOMEM, EDEVICE, ESINGULAR, EBUDGET, ECAPACITY, ENOTFOUND = -1, -2, -3, 
 ROLLOUT_NONFINITE, ROLLOUT_CAPACITY, ROLLOUT_BADFIELD = 1, 2, 4
 SHED_BOTH, SHED_TE, SHED_NONE = 0, 1, 2
 FP32C, FP64 = 0, 1
+PATH_AUTO, PATH_LDS, PATH_STREAM = 0, 1, 2
 
 _P = C.c_void_p
 _D = C.c_double
@@ -65,6 +66,7 @@ def lib():
                                         C.POINTER(BatchOut), _P]
         L.vpm_plate_solve.argtypes = [_P, C.POINTER(Params), _I, _P, _P, _P, _I, _P, _P]
         L.mppi_weights.argtypes = [_P, _I, _I, _P, _D, _P, _P, _P, _P, _P, _P, _P]
+        L.vpm_set_path.argtypes = [_P, C.c_int]
         L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
         L.vpm_pair_count.restype = C.c_int64
         _lib = L
@@ -205,6 +207,10 @@ class Context:
         check(lib().vpm_create(C.byref(h), int(device)), "vpm_create")
         self.h = h
         self.device = device
+
+    def set_path(self, path: int):
+        """Select the rollout kernel variant (PATH_AUTO / PATH_LDS / PATH_STREAM)."""
+        check(lib().vpm_set_path(self.h, int(path)), "vpm_set_path")
 
     def close(self):
         if self.h:
