@@ -108,10 +108,15 @@ VPM_API int vpm_create(vpm_ctx **out, int device) {
   (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device);
   c->max_lds = lds > optin ? lds : optin;
   if (c->max_lds <= 0) c->max_lds = 65536;
-  if (hipSetDevice(device) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) != hipSuccess) {
-    delete c;
-    return fail(VPM_EDEVICE, "hipEventCreate failed");
+  bool ok = hipSetDevice(device) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->fork_event, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < 3 && ok; ++i)
+    ok = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&c->join_event[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    vpm_destroy(c);
+    return fail(VPM_EDEVICE, "stream or event creation failed");
   }
   *out = c;
   return VPM_OK;
@@ -131,7 +136,13 @@ VPM_API void vpm_destroy(vpm_ctx *ctx) {
   (void)hipDeviceSynchronize();
   for (auto &kv : ctx->plate_cache) (void)hipFree(kv.second);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->plan) (void)hipFree(ctx->plan);
   if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
+  if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
+  for (int i = 0; i < 3; ++i) {
+    if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+    if (ctx->join_event[i]) (void)hipEventDestroy(ctx->join_event[i]);
+  }
   delete ctx;
 }
 

@@ -84,6 +84,7 @@ template <typename R> struct Shared {
   double gb_prev[kMaxBound];
   double bvec[kMaxBound + 2];
   int head, n_w, status;
+  int claimed;  // rollout claimed from the work queue
   int pa[kMaxPairs], pb[kMaxPairs];
   long long pairs;
 };
@@ -527,12 +528,38 @@ __device__ void finish(const KArgs &a, const Shared<R> &sh,
   }
 }
 
+// --------------------------------------------------------- work queues
+
+// A persistent workgroup claims its next rollout: list[next[cls]++] while
+// below range[cls].y (the class's slice of the planned order). With no list
+// it takes rollout `fallback` once.
+struct Queue {
+  const int32_t *list;  // rollout order (classes contiguous, longest first)
+  int32_t *next;        // per-class cursor into `list`
+  const int2 *range;    // per-class [begin, end) of `list`
+  int cls;
+};
+
+template <typename R>
+__device__ inline int claim(const Queue &q, Shared<R> &sh, int tid,
+                            int &fallback) {
+  if (!q.list) {
+    const int k = fallback;
+    fallback = -1;
+    return k;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int idx = atomicAdd(&q.next[q.cls], 1);
+    sh.claimed = idx < q.range[q.cls].y ? q.list[idx] : -1;
+  }
+  __syncthreads();
+  return sh.claimed;
+}
+
 // ---------------------------------------------------------------- LDS path
 
-constexpr int kLdsWaves = 4;
-constexpr int kLdsThreads = 64 * kLdsWaves;
-
-template <typename R, int T>
+template <typename R, int T, int NW>
 __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
                                  const typename SrcOf<R>::type *src, Vec2<R> *red,
                                  int c0, int NT, int head, int s_lo, int s_hi,
@@ -550,11 +577,13 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
 }
 
-// MINW: waves per SIMD the register budget must allow (4 for FP32 fills a CU
-// with four rollouts; FP64 takes 2 to avoid spills).
-template <typename R, int TMAX, int MINW>
-__global__ __launch_bounds__(kLdsThreads, MINW) void rollout_lds_kernel(KArgs a) {
+// LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
+// sources into NW contiguous slices (one per wave) and adds the slices in
+// FP64 in wave order. MINW: waves per SIMD the register budget must allow.
+template <typename R, int TMAX, int MINW, int NW>
+__global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
+  constexpr int kThr = 64 * NW;
   extern __shared__ __align__(32) unsigned char lds[];
   __shared__ Shared<R> sh;
   Src *src = reinterpret_cast<Src *>(lds);
@@ -563,61 +592,65 @@ __global__ __launch_bounds__(kLdsThreads, MINW) void rollout_lds_kernel(KArgs a)
   Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(lds + a.off_vel);
   double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
 
-  const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n_surf = 2 * a.nb + 3;
-  if (!setup(a, sh, src, k, tid, kLdsThreads)) return;
-  for (int q = tid; q < a.S * a.S; q += kLdsThreads) kinv[q] = a.kinv_t[q];
-  __syncthreads();
+  for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
+  int fallback = blockIdx.x;
+  for (;;) {
+    const int k = claim(qu, sh, tid, fallback);
+    if (k < 0) break;
+    __syncthreads();
+    if (!setup(a, sh, src, k, tid, kThr)) continue;
+    __syncthreads();
 
-  for (int n = 0; n < a.H; ++n) {
-    if (n == 0) {
-      if (tid == 0) prologue(a, sh, src);
-      __syncthreads();
-    }
-    const int head = sh.head, n_w = sh.n_w;
-    const int NT = n_surf + n_w;
-
-    // pass A: each wave takes a contiguous quarter of the sources
-    const int s_lo = head + (n_w * wave) / kLdsWaves;
-    const int s_hi = head + (n_w * (wave + 1)) / kLdsWaves;
-    for (int c0 = 0; c0 < NT;) {
-      const int rem = NT - c0;
-      int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
-      while (T > 1 && 64 * T > rem) T >>= 1;
-      switch (T) {
-        case 1: lds_pass_a_chunk<R, 1>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-        case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-        default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+    for (int n = 0; n < a.H; ++n) {
+      if (n == 0) {
+        if (tid == 0) prologue(a, sh, src);
+        __syncthreads();
       }
-      __syncthreads();
-      const int span = 64 * T;
-      for (int t = tid; t < span && c0 + t < NT; t += kLdsThreads) {
-        double vx = 0.0, vz = 0.0;
-#pragma unroll
-        for (int w = 0; w < kLdsWaves; ++w) {
-          const Vec2<R> r = red[w * span + t];
-          vx += double(r.x);
-          vz += double(r.z);
+      const int head = sh.head, n_w = sh.n_w;
+      const int NT = n_surf + n_w;
+
+      const int s_lo = head + (n_w * wave) / NW;
+      const int s_hi = head + (n_w * (wave + 1)) / NW;
+      for (int c0 = 0; c0 < NT;) {
+        const int rem = NT - c0;
+        int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
+        while (T > 1 && 64 * T > rem) T >>= 1;
+        switch (T) {
+          case 1: lds_pass_a_chunk<R, 1, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+          case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+          default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
         }
-        const int tt = c0 + t;
-        if (tt < n_surf)
-          vsurf[tt] = make_double2(vx, vz);
-        else
-          vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};
+        __syncthreads();
+        const int span = 64 * T;
+        for (int t = tid; t < span && c0 + t < NT; t += kThr) {
+          double vx = 0.0, vz = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            const Vec2<R> r = red[w * span + t];
+            vx += double(r.x);
+            vz += double(r.z);
+          }
+          const int tt = c0 + t;
+          if (tt < n_surf)
+            vsurf[tt] = make_double2(vx, vz);
+          else
+            vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};
+        }
+        __syncthreads();
+        c0 += span;
       }
-      __syncthreads();
-      c0 += span;
-    }
 
-    if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
-    __syncthreads();
-    pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kLdsThreads);
-    __syncthreads();
-    if (tid == 0) epilogue(a, sh, src, k, n, n_w);
-    __syncthreads();
+      if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
+      __syncthreads();
+      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr);
+      __syncthreads();
+      if (tid == 0) epilogue(a, sh, src, k, n, n_w);
+      __syncthreads();
+    }
+    finish(a, sh, src, k, tid, kThr);
   }
-  finish(a, sh, src, k, tid, kLdsThreads);
 }
 
 // ---------------------------------------------------------- streaming path
@@ -656,10 +689,11 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
   }
 }
 
-// Persistent: workgroup b runs rollouts b, b + G, b + 2G, ... with its wake in
-// workspace slot b (a.cap entries of sources and of velocities).
+// Persistent: each workgroup keeps its rollout's wake in workspace slot
+// blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
+// or, with a queue, claims them in planned order.
 template <typename R, int TMAX, int NW>
-__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a) {
+__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
   extern __shared__ __align__(32) unsigned char lds[];
@@ -674,7 +708,16 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a) {
   const int n_surf = 2 * a.nb + 3;
   for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
 
-  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+  int next_static = blockIdx.x;
+  for (;;) {
+    int k;
+    if (qu.list) {
+      k = claim(qu, sh, tid, next_static);
+    } else {
+      k = next_static < a.K ? next_static : -1;
+      next_static += gridDim.x;
+    }
+    if (k < 0) break;
     __syncthreads();
     if (!setup(a, sh, src, k, tid, kThr)) continue;
     __syncthreads();
@@ -709,10 +752,69 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a) {
   }
 }
 
+// ------------------------------------------------------- batch planning
+
+constexpr int kPlanThreads = 1024;
+constexpr int kBuckets = 128;  // 4 per octave of capacity
+constexpr int kClasses = 3;    // 0: streamed, 1: large LDS, 2: small LDS
+
+// One workgroup orders an uneven batch: the class of rollout k follows its
+// capacity n0 + 2H (streamed above cap_l, large LDS above cap_s, small LDS
+// otherwise); within a class rollouts are ordered by decreasing capacity in
+// quarter-octave buckets (longest processing time first). Writes the order
+// into list, the per-class slices into range and resets the cursors.
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(
+    int K, int H, int max_wake0, int n_fields, const int64_t *field_off,
+    const int32_t *field_of, int cap_s, int cap_l, int32_t *list, int2 *range,
+    int32_t *next) {
+  __shared__ int hist[kClasses * kBuckets];
+  __shared__ int cursor[kClasses * kBuckets];
+  const int t = threadIdx.x;
+  for (int i = t; i < kClasses * kBuckets; i += kPlanThreads) hist[i] = 0;
+  __syncthreads();
+  auto key_of = [&](int k) -> int {
+    const int fo = field_of ? field_of[k] : k;
+    int cap = 0;
+    if (fo >= 0 && fo < n_fields) {
+      const long long n0 = field_off[fo + 1] - field_off[fo];
+      if (n0 >= 0 && n0 <= max_wake0) cap = static_cast<int>(n0) + 2 * H;
+    }
+    const int cls = cap > cap_l ? 0 : cap > cap_s ? 1 : 2;
+    int b = cap > 0 ? static_cast<int>(4.0f * log2f(static_cast<float>(cap))) : 0;
+    b = b < 0 ? 0 : b >= kBuckets ? kBuckets - 1 : b;
+    return cls * kBuckets + (kBuckets - 1 - b);  // larger capacity first
+  };
+  for (int k = t; k < K; k += kPlanThreads) atomicAdd(&hist[key_of(k)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int c = 0; c < kClasses; ++c) {
+      const int begin = acc;
+      for (int b = 0; b < kBuckets; ++b) {
+        cursor[c * kBuckets + b] = acc;
+        acc += hist[c * kBuckets + b];
+      }
+      range[c] = make_int2(begin, acc);
+      next[c] = begin;
+    }
+  }
+  __syncthreads();
+  for (int k = t; k < K; k += kPlanThreads) list[atomicAdd(&cursor[key_of(k)], 1)] = k;
+}
+
 // ------------------------------------------------------------------ host
 
 template <typename R>
-int lds_layout(int cap, int nb, int tmax, KArgs &a) {
+size_t lds_fixed_bytes(int nb, int S, int nw, int tmax) {
+  return (size_t)S * S * sizeof(double) + (size_t)(2 * nb + 3) * sizeof(double2) +
+         (size_t)nw * 64 * tmax * sizeof(Vec2<R>) + 32 + sizeof(Shared<R>);
+}
+template <typename R> constexpr size_t lds_per_vortex() {
+  return sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>);
+}
+
+template <typename R>
+int lds_layout(int cap, int nb, int nw, int tmax, KArgs &a) {
   size_t off = 0;
   off += (size_t)cap * sizeof(typename SrcOf<R>::type);
   off = (off + 15) & ~size_t(15);
@@ -721,7 +823,7 @@ int lds_layout(int cap, int nb, int tmax, KArgs &a) {
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = static_cast<int>(off);
-  off += (size_t)kLdsWaves * 64 * tmax * sizeof(Vec2<R>);
+  off += (size_t)nw * 64 * tmax * sizeof(Vec2<R>);
   a.off_vel = static_cast<int>(off);
   off += (size_t)cap * sizeof(Vec2<R>);
   return static_cast<int>(off);
@@ -747,57 +849,152 @@ int set_lds(Kern kern, int bytes) {
   return VPM_OK;
 }
 
-template <typename R, int TMAX, int MINW>
-int launch_lds(vpm_ctx *ctx, KArgs &a, hipStream_t stream, bool *fits) {
-  const int lds = lds_layout<R>(a.cap, a.nb, TMAX, a);
-  *fits = lds + static_cast<int>(sizeof(Shared<R>)) <= ctx->max_lds;
-  if (!*fits) return VPM_OK;
-  auto kern = rollout_lds_kernel<R, TMAX, MINW>;
+// Launch the LDS kernel for wakes up to `cap` vortices; grid = `grid`
+// workgroups (one per rollout without a queue).
+template <typename R, int TMAX, int MINW, int NW>
+int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
+               hipStream_t stream) {
+  a.cap = cap;
+  const int lds = lds_layout<R>(cap, a.nb, NW, TMAX, a);
+  if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
+    return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
+                                   " does not fit the LDS-resident kernel");
+  auto kern = rollout_lds_kernel<R, TMAX, MINW, NW>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
-  hipLaunchKernelGGL(kern, dim3(a.K), dim3(kLdsThreads), lds, stream, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a, qu);
   VPM_HIP_TRY(hipGetLastError());
   return VPM_OK;
 }
 
-// Grow the context's streaming workspace to `bytes` (device-synchronises
-// before freeing a smaller one).
-int ensure_workspace(vpm_ctx *ctx, size_t bytes) {
-  if (ctx->ws_bytes >= bytes) return VPM_OK;
-  if (ctx->ws) {
+// Grow a context buffer to `bytes` (device-synchronises before freeing a
+// smaller one).
+int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what) {
+  if (*have >= bytes) return VPM_OK;
+  if (*buf) {
     VPM_HIP_TRY(hipDeviceSynchronize());
-    VPM_HIP_TRY(hipFree(ctx->ws));
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
+    VPM_HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
   }
-  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
-    ctx->ws = nullptr;
-    return fail(VPM_ENOMEM, "hipMalloc of the streaming workspace failed");
+  if (hipMalloc(buf, bytes) != hipSuccess) {
+    *buf = nullptr;
+    return fail(VPM_ENOMEM, std::string("hipMalloc of the ") + what + " failed");
   }
-  ctx->ws_bytes = bytes;
+  *have = bytes;
   return VPM_OK;
 }
 
 template <typename R, int TMAX, int NW>
-int launch_stream(vpm_ctx *ctx, KArgs &a, hipStream_t stream) {
+int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
+                  hipStream_t stream) {
   const int lds = stream_layout<R>(a.nb, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
   auto kern = rollout_stream_kernel<R, TMAX, NW>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
-  const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
   const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
-  std::lock_guard<std::mutex> lock(ctx->ws_mu);
-  rc = ensure_workspace(ctx, slot * grid);
+  rc = ensure_buffer(&ctx->ws, &ctx->ws_bytes, slot * grid, "streaming workspace");
   if (rc != VPM_OK) return rc;
-  // calls that share the workspace are ordered across streams
-  if (ctx->ws_event_valid) VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
   a.ws_src = ctx->ws;
   a.ws_vel = static_cast<char *>(ctx->ws) +
              (size_t)grid * a.cap * sizeof(typename SrcOf<R>::type);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a, qu);
   VPM_HIP_TRY(hipGetLastError());
+  return VPM_OK;
+}
+
+// Largest capacity a workgroup of the LDS kernel can hold within `bytes`.
+template <typename R>
+int lds_capacity(int nb, int S, int nw, int tmax, size_t bytes) {
+  const size_t fixed = lds_fixed_bytes<R>(nb, S, nw, tmax);
+  return bytes > fixed ? static_cast<int>((bytes - fixed) / lds_per_vortex<R>()) : 0;
+}
+
+// One batch in a given precision. Uniform batches (one field) run one
+// rollout per workgroup on the caller's stream. Uneven batches are planned
+// on the device and run as up to three persistent class kernels on forked
+// streams, joined back into the caller's stream.
+template <typename R, int TMAX_S, int MINW_S, int TMAX_L, int TMAX_X, int NW_X>
+int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
+  // FP32 takes 16-wave large-class workgroups (128 VGPRs each), FP64 8
+  constexpr int kNwSmall = 4, kNwLarge = sizeof(R) == 4 ? 16 : 8;
+  const int cap = a.cap;  // max_wake0 + 2H
+  const int cap_small = lds_capacity<R>(a.nb, a.S, kNwSmall, TMAX_S, ctx->max_lds / 4);
+  const int cap_large = lds_capacity<R>(a.nb, a.S, kNwLarge, TMAX_L, ctx->max_lds);
+  const int cap_lds_small_max = lds_capacity<R>(a.nb, a.S, kNwSmall, TMAX_S, ctx->max_lds);
+  const Queue none{nullptr, nullptr, nullptr, 0};
+  const bool stream_only = path == VPM_PATH_STREAM;
+  if (a.n_fields == 1 || path == VPM_PATH_LDS || stream_only) {
+    if (!stream_only && cap <= cap_small)
+      return launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream);
+    if (!stream_only && cap <= cap_large)
+      return launch_lds<R, TMAX_L, 1, kNwLarge>(ctx, a, cap, a.K, none, stream);
+    if (!stream_only && cap <= cap_lds_small_max)
+      return launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream);
+    if (path == VPM_PATH_LDS)
+      return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
+                                     " does not fit the LDS-resident kernel");
+    std::lock_guard<std::mutex> lock(ctx->ws_mu);
+    if (ctx->ws_event_valid) VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
+    const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
+    int rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, none, stream);
+    if (rc != VPM_OK) return rc;
+    VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
+    ctx->ws_event_valid = true;
+    return VPM_OK;
+  }
+
+  // uneven batch: plan, then the class kernels
+  std::lock_guard<std::mutex> lock(ctx->ws_mu);
+  if (ctx->ws_event_valid) VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
+  const size_t plan_bytes = (size_t)a.K * sizeof(int32_t) + 64;
+  int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan");
+  if (rc != VPM_OK) return rc;
+  int2 *range = static_cast<int2 *>(ctx->plan);
+  int32_t *next = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->plan) + 32);
+  int32_t *list = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->plan) + 64);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, a.K, a.H,
+                     a.max_wake0, a.n_fields, a.field_off, a.field_of, cap_small,
+                     cap_large, list, range, next);
+  VPM_HIP_TRY(hipGetLastError());
+  VPM_HIP_TRY(hipEventRecord(ctx->fork_event, stream));
+  hipEvent_t joins[kClasses];
+  int n_join = 0;
+  // class 0: streamed (only when some rollout can exceed the large class)
+  if (cap > cap_large) {
+    hipStream_t s = ctx->side[0];
+    VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
+    const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
+    rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, Queue{list, next, range, 0}, s);
+    if (rc != VPM_OK) return rc;
+    VPM_HIP_TRY(hipEventRecord(ctx->join_event[0], s));
+    joins[n_join++] = ctx->join_event[0];
+  }
+  // class 1: large rollouts, 16-wave LDS workgroups, one per CU
+  if (cap > cap_small) {
+    hipStream_t s = ctx->side[1];
+    VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
+    const int c1 = cap < cap_large ? cap : cap_large;
+    const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
+    rc = launch_lds<R, TMAX_L, 1, kNwLarge>(ctx, a, c1, grid, Queue{list, next, range, 1}, s);
+    if (rc != VPM_OK) return rc;
+    VPM_HIP_TRY(hipEventRecord(ctx->join_event[1], s));
+    joins[n_join++] = ctx->join_event[1];
+  }
+  // class 2: small rollouts, 4-wave LDS workgroups, four per CU
+  {
+    hipStream_t s = ctx->side[2];
+    VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
+    const int c2 = cap < cap_small ? cap : cap_small;
+    const int grid = a.K < 4 * ctx->n_cu ? a.K : 4 * ctx->n_cu;
+    rc = launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, c2, grid, Queue{list, next, range, 2}, s);
+    if (rc != VPM_OK) return rc;
+    VPM_HIP_TRY(hipEventRecord(ctx->join_event[2], s));
+    joins[n_join++] = ctx->join_event[2];
+  }
+  for (int i = 0; i < n_join; ++i) VPM_HIP_TRY(hipStreamWaitEvent(stream, joins[i], 0));
   VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
   ctx->ws_event_valid = true;
   return VPM_OK;
@@ -861,19 +1058,9 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.wg_out = wake ? out->wg : nullptr;
   a.vel_last = wake ? out->vel_last : nullptr;
   a.n_vel_last = out->n_vel_last;
-  const bool fp64 = p->precision == VPM_FP64;
-  const int path = ctx->path;
-  if (path != VPM_PATH_STREAM) {
-    bool fits = false;
-    const int rc = fp64 ? launch_lds<double, 2, 2>(ctx, a, stream, &fits)
-                        : launch_lds<float, 4, 4>(ctx, a, stream, &fits);
-    if (rc != VPM_OK || fits) return rc;
-    if (path == VPM_PATH_LDS)
-      return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(a.cap) +
-                                     " does not fit the LDS-resident kernel");
-  }
-  return fp64 ? launch_stream<double, 2, 8>(ctx, a, stream)
-              : launch_stream<float, 4, 16>(ctx, a, stream);
+  if (p->precision == VPM_FP64)
+    return run_batch<double, 2, 2, 2, 2, 8>(ctx, a, ctx->path, stream);
+  return run_batch<float, 4, 4, 2, 4, 16>(ctx, a, ctx->path, stream);
 }
 
 }  // namespace vpm

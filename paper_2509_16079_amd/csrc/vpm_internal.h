@@ -66,8 +66,15 @@ struct vpm_ctx {
   std::mutex ws_mu;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  void *plan = nullptr;  // uneven-batch order and class cursors
+  size_t plan_bytes = 0;
   hipEvent_t ws_event = nullptr;
   bool ws_event_valid = false;
+  // forked streams for the class kernels of an uneven batch (default
+  // priority) and the events that fork and join them
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork_event = nullptr;
+  hipEvent_t join_event[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace vpm {
