@@ -200,6 +200,79 @@ VPM_API int mppi_weights(vpm_ctx *ctx, int32_t K, int32_t H, const double *cost,
                          const double *u_eps, double *w_out, double *u_new,
                          int32_t *argmin, double *jmin, void *stream);
 
+/* ------------------------------------------------------------ planner
+ * A replanning service: fluid and vehicle states stay resident on the
+ * device; requests (one MPPI iteration of the planner's hot path, Sec. IV-A:
+ * K rollouts of H steps from a resident state, costs and the softmin
+ * update) are admitted in arrival order while a slot is free and the sum of
+ * in-flight footprints stays within the HBM budget, and admitted requests
+ * run concurrently on separate streams, so work that arrives while others
+ * are on the GPU overlaps with it. All planner calls are thread-safe. */
+typedef struct planner planner;
+
+typedef struct {
+  int32_t device;           /* HIP device index                              */
+  int32_t max_slots;        /* requests in flight at once, 1..16 (1 = serial) */
+  size_t hbm_budget_bytes;  /* admission budget for in-flight footprints      */
+} planner_opts;
+
+typedef struct {
+  uint64_t state_id;        /* resident state from planner_state_put         */
+  vpm_params params;        /* model parameters (n_bound must match the state) */
+  int32_t K, H;             /* rollouts and steps                            */
+  double dt;                /* step [s]                                      */
+  double lambda;            /* MPPI temperature (Eq. 25), > 0                */
+  double x_goal[7];         /* cost goal (Eq. 24)                            */
+  double q_diag[7];         /* cost weights (Eq. 24)                         */
+  const double *u_mean;     /* host [H]: copied at submit                    */
+  const double *u_eps;      /* host [K][H]: copied at submit                 */
+} plan_req;
+
+typedef struct {
+  int32_t status;           /* VPM_OK, or the error the request failed with  */
+  int32_t argmin;           /* MPPI argmin (-1 if no finite cost)            */
+  double jmin;
+  double *u_new;            /* host [H] caller buffer for the update, or NULL */
+  double *w;                /* host [K] caller buffer for the weights, or NULL */
+  double *cost;             /* host [K] caller buffer for the costs, or NULL  */
+  double *g_final;          /* host [K][7] caller buffer, or NULL            */
+  double t_arrive_us;       /* submit time (us since planner_create)        */
+  double t_admit_us;        /* admission time                               */
+  double t_done_us;         /* completion time (results in host memory)     */
+  int64_t pairs;            /* pair-interactions of the request             */
+} plan_result;
+
+/* Create / destroy a planner (it owns one context and stream per slot).
+ * planner_destroy waits for in-flight requests. */
+VPM_API int planner_create(planner **out, const planner_opts *opts);
+VPM_API void planner_destroy(planner *p);
+
+/* Upload a fluid and vehicle state and keep it resident: n vortices (host
+ * arrays, age order), glider state g7 (host [7]) and previous bound
+ * circulations gb (host [n_bound]). Returns its id in *state_id. */
+VPM_API int planner_state_put(planner *p, int32_t n, const double *wx,
+                              const double *wz, const double *wg,
+                              const double *g7, int32_t n_bound,
+                              const double *gb, uint64_t *state_id);
+VPM_API int planner_state_drop(planner *p, uint64_t state_id);
+
+/* Queue a request; its inputs are copied, so the caller may reuse them on
+ * return. Returns a ticket. Errors: VPM_EINVAL, VPM_ENOTFOUND (state),
+ * VPM_EBUDGET (the request alone exceeds the budget). */
+VPM_API int planner_submit(planner *p, const plan_req *req, uint64_t *ticket);
+
+/* Wait up to timeout_us (0: do not wait, < 0: forever) for a request.
+ * Returns VPM_PENDING, or VPM_OK after filling *res (the ticket is then
+ * released), or VPM_ENOTFOUND. */
+VPM_API int planner_poll(planner *p, uint64_t ticket, plan_result *res,
+                         int32_t timeout_us);
+
+/* Device-memory footprint the planner charges a request against its budget
+ * (host arithmetic): inputs, outputs and, for wakes beyond the LDS-resident
+ * kernel, the streaming workspace. */
+VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0,
+                                 int32_t n_bound);
+
 /* Exact pair-interaction count of one rollout (host arithmetic): per step
  * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b
  * bound pairs with N_w' = N_w + 2, merging above n_wake_max (> 0). */

@@ -1002,6 +1002,10 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 
 }  // namespace
 
+int lds_resident_capacity(int nb) {
+  return lds_capacity<float>(nb, nb + 2, 4, 4, 163840);
+}
+
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
                    vpm_batch_out *out, const double *kinv_t,
                    hipStream_t stream) {

@@ -83,6 +83,10 @@ namespace vpm {
 int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
                          const double **out);
 
+// Largest FP32 wake capacity (N_0 + 2H) the LDS-resident kernel holds on a
+// gfx950 workgroup (160 KB of LDS); larger wakes take the streaming kernel.
+int lds_resident_capacity(int nb);
+
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
                    vpm_batch_out *out, const double *kinv_t,
                    hipStream_t stream);

@@ -266,3 +266,113 @@ def run_workload(ctx: Context, wl, precision=FP32C, **want) -> dict:
     ctx.rollout(wl.params, db, out, precision)
     torch.cuda.synchronize()
     return out.to_numpy()
+
+
+# ----------------------------------------------------------------- planner
+
+class PlannerOpts(C.Structure):
+    _fields_ = [("device", _I), ("max_slots", _I), ("hbm_budget_bytes", C.c_size_t)]
+
+
+class PlanReq(C.Structure):
+    _fields_ = [("state_id", C.c_uint64), ("params", Params), ("K", _I), ("H", _I), ("dt", _D),
+                ("lam", _D), ("x_goal", _D * 7), ("q_diag", _D * 7), ("u_mean", _P),
+                ("u_eps", _P)]
+
+
+class PlanResult(C.Structure):
+    _fields_ = [("status", _I), ("argmin", _I), ("jmin", _D), ("u_new", _P), ("w", _P),
+                ("cost", _P), ("g_final", _P), ("t_arrive_us", _D), ("t_admit_us", _D),
+                ("t_done_us", _D), ("pairs", C.c_int64)]
+
+
+def _planner_lib():
+    L = lib()
+    if not getattr(L, "_planner_ready", False):
+        L.planner_create.argtypes = [C.POINTER(_P), C.POINTER(PlannerOpts)]
+        L.planner_destroy.argtypes = [_P]
+        L.planner_destroy.restype = None
+        L.planner_state_put.argtypes = [_P, _I, _P, _P, _P, _P, _I, _P, C.POINTER(C.c_uint64)]
+        L.planner_state_drop.argtypes = [_P, C.c_uint64]
+        L.planner_submit.argtypes = [_P, C.POINTER(PlanReq), C.POINTER(C.c_uint64)]
+        L.planner_poll.argtypes = [_P, C.c_uint64, C.POINTER(PlanResult), _I]
+        L.planner_footprint.argtypes = [_I, _I, _I, _I]
+        L.planner_footprint.restype = C.c_size_t
+        L._planner_ready = True
+    return L
+
+
+def planner_footprint(K, H, n0, n_bound):
+    return int(_planner_lib().planner_footprint(int(K), int(H), int(n0), int(n_bound)))
+
+
+class Planner:
+    """The replanning service (``planner_*`` of the C ABI)."""
+
+    def __init__(self, device=0, max_slots=4, budget_bytes=64 << 30):
+        L = _planner_lib()
+        o = PlannerOpts(int(device), int(max_slots), int(budget_bytes))
+        h = C.c_void_p()
+        check(L.planner_create(C.byref(h), C.byref(o)), "planner_create")
+        self.h = h
+        self._shape = {}
+
+    def close(self):
+        if self.h:
+            _planner_lib().planner_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def put_state(self, wx, wz, wg, g7, gb):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        wx, wz, wg, g7, gb = f(wx), f(wz), f(wg), f(g7), f(gb)
+        sid = C.c_uint64()
+        p = lambda a: a.ctypes.data if a.size else None
+        check(_planner_lib().planner_state_put(self.h, wx.size, p(wx), p(wz), p(wg), p(g7),
+                                               gb.size, p(gb), C.byref(sid)), "planner_state_put")
+        return sid.value
+
+    def drop_state(self, sid):
+        check(_planner_lib().planner_state_drop(self.h, int(sid)), "planner_state_drop")
+
+    def submit(self, sid, params: dict, u_mean, u_eps, dt, lam=1.0, x_goal=None, q_diag=None,
+               precision=FP32C):
+        u_mean = np.ascontiguousarray(u_mean, dtype=np.float64)
+        u_eps = np.ascontiguousarray(u_eps, dtype=np.float64)
+        K, H = u_eps.shape
+        r = PlanReq()
+        r.state_id = int(sid)
+        r.params = make_params(params, precision)
+        r.K, r.H, r.dt, r.lam = K, H, float(dt), float(lam)
+        from . import workloads as W
+        xg = W.X_GOAL if x_goal is None else x_goal
+        qd = W.Q_POS_PITCH if q_diag is None else q_diag
+        for i in range(7):
+            r.x_goal[i] = float(xg[i])
+            r.q_diag[i] = float(qd[i])
+        r.u_mean, r.u_eps = u_mean.ctypes.data, u_eps.ctypes.data
+        t = C.c_uint64()
+        check(_planner_lib().planner_submit(self.h, C.byref(r), C.byref(t)), "planner_submit")
+        self._shape[t.value] = (K, H)
+        return t.value
+
+    def poll(self, ticket, timeout_us=-1):
+        """Result dict, or None if still pending after the timeout."""
+        K, H = self._shape.get(ticket, (0, 0))   # unknown tickets: the library says so
+        out = dict(u_new=np.zeros(H), w=np.zeros(K), cost=np.zeros(K), g_final=np.zeros((K, 7)))
+        r = PlanResult()
+        r.u_new, r.w = out["u_new"].ctypes.data, out["w"].ctypes.data
+        r.cost, r.g_final = out["cost"].ctypes.data, out["g_final"].ctypes.data
+        rc = check(_planner_lib().planner_poll(self.h, int(ticket), C.byref(r), int(timeout_us)),
+                   "planner_poll")
+        if rc == PENDING:
+            return None
+        self._shape.pop(ticket, None)
+        out.update(status=r.status, argmin=r.argmin, jmin=r.jmin, t_arrive_us=r.t_arrive_us,
+                   t_admit_us=r.t_admit_us, t_done_us=r.t_done_us, pairs=r.pairs)
+        return out

@@ -1,0 +1,131 @@
+"""GPU: the replanning service. Results of served requests equal the same
+computation issued directly (bitwise, alone or in any mix); admission
+respects the HBM budget; errors surface as status codes."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2509_16079_amd import vpm as V
+from paper_2509_16079_amd import workloads as W
+from tests.parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _states(n_states=3, seed=11):
+    rng = np.random.default_rng(seed)
+    return [W.random_field(np.random.Generator(np.random.Philox(seed + i)),
+                           int(rng.integers(300, 1500))) for i in range(n_states)]
+
+
+def _requests(n, n_states, seed=5):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        K, H = int(rng.integers(32, 257)), int(rng.integers(8, 31))
+        out.append(dict(state=int(rng.integers(0, n_states)), K=K, H=H,
+                        eps=W.f32(rng.normal(0, 0.15, (K, H))), mu=W.f32(rng.normal(0, 0.05, H))))
+    return out
+
+
+def _direct(ctx, params, state, req):
+    wl = W.workload_from_state("direct", params, state, K=req["K"], H=req["H"], eps=req["eps"])
+    wl.u_mean = req["mu"]
+    db = V.DeviceBatch(wl)
+    out = V.DeviceOutputs(db)
+    ctx.rollout(params, db, out, V.FP32C)
+    w, un, am, jm = ctx.mppi(out.cost, 1.0, db.u_mean, db.u_eps)
+    torch.cuda.synchronize()
+    return dict(cost=out.cost.cpu().numpy(), w=w.cpu().numpy(), u_new=un.cpu().numpy(),
+                argmin=int(am.item()), g_final=out.g_final.cpu().numpy())
+
+
+def _serve(planner, sids, params, reqs):
+    g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
+    dt = float(W.f32(0.005))      # the step the direct calls use
+    tickets = [planner.submit(sids[r["state"]], params, r["mu"], r["eps"], dt) for r in reqs]
+    return [planner.poll(t, timeout_us=-1) for t in tickets]
+
+
+def test_served_results_equal_direct_calls_alone_and_in_the_mix():
+    params = W.make_params(32)
+    states = _states()
+    reqs = _requests(10, len(states))
+    g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
+    mix = V.Planner(max_slots=4)
+    alone = V.Planner(max_slots=1)
+    try:
+        sids = [mix.put_state(*s, g0, np.zeros(32)) for s in states]
+        sids1 = [alone.put_state(*s, g0, np.zeros(32)) for s in states]
+        served = _serve(mix, sids, params, reqs)
+        serial = _serve(alone, sids1, params, reqs)
+        ctx = V.Context(0)
+        for r, a, b in zip(reqs, served, serial):
+            d = _direct(ctx, params, states[r["state"]], r)
+            assert a["status"] == 0 and b["status"] == 0
+            for key in ("cost", "w", "u_new", "g_final"):
+                assert np.array_equal(a[key], d[key]), key
+                assert np.array_equal(b[key], d[key]), key
+            assert a["argmin"] == d["argmin"] == b["argmin"]
+            assert a["pairs"] == r["K"] * V.pair_count(len(states[r["state"]][0]), r["H"], 32, 0)
+            assert a["t_arrive_us"] <= a["t_admit_us"] <= a["t_done_us"]
+        ctx.close()
+        # with four slots, some requests ran concurrently
+        iv = sorted((s["t_admit_us"], s["t_done_us"]) for s in served)
+        assert any(iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
+    finally:
+        mix.close()
+        alone.close()
+
+
+def test_budget_admits_one_request_at_a_time():
+    params = W.make_params(32)
+    states = _states(1)
+    reqs = _requests(6, 1, seed=9)
+    for r in reqs:                                 # equal footprints: 1.5 of one fits one
+        r["eps"], r["mu"] = r["eps"][:32, :8], r["mu"][:8]
+    fp = V.planner_footprint(32, 8, len(states[0][0]), 32)
+    p = V.Planner(max_slots=4, budget_bytes=fp + fp // 2)
+    try:
+        g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
+        sids = [p.put_state(*s, g0, np.zeros(32)) for s in states]
+        res = _serve(p, sids, params, reqs)
+        iv = sorted((s["t_admit_us"], s["t_done_us"]) for s in res)
+        assert all(iv[i + 1][0] >= iv[i][1] for i in range(len(iv) - 1))
+        with pytest.raises(V.VpmError) as e:
+            p.submit(sids[0], params, np.zeros(400), np.zeros((4096, 400)), 0.005)
+        assert e.value.code == V.EBUDGET
+    finally:
+        p.close()
+
+
+def test_errors_and_oracle_check():
+    params = W.make_params(16, n_wake_max=200)
+    wl = W.plain_single_plan(K=16, H=12)
+    p = V.Planner(max_slots=2)
+    try:
+        sid = p.put_state(wl.wx, wl.wz, wl.wg, wl.g0[0], np.zeros(16))
+        with pytest.raises(V.VpmError) as e:
+            p.submit(sid + 99, params, wl.u_mean, wl.u_eps, wl.dt)
+        assert e.value.code == V.ENOTFOUND
+        with pytest.raises(V.VpmError) as e:
+            p.submit(sid, W.make_params(32), wl.u_mean, wl.u_eps, wl.dt)
+        assert e.value.code == V.EINVAL
+        t = p.submit(sid, params, wl.u_mean, wl.u_eps, wl.dt)
+        r = p.poll(t)
+        assert r["status"] == 0
+        wl.pairs = np.full((wl.K, 2), -1, dtype=np.int32)    # the state carries no pair tags
+        o = O.rollout_batch(wl.params, wl.K, wl.H, wl.dt, wl.g0, wl.gb0, wl.field_off,
+                            wl.field_of, wl.wx, wl.wz, wl.wg, wl.pairs, wl.u, wl.x_goal,
+                            wl.q_diag)
+        assert rel_l2(r["g_final"], o["g_final"]) <= 1e-4
+        ref = O.mppi(o["cost"], 1.0, wl.u_mean, wl.u)
+        assert r["argmin"] == ref["argmin"]
+        assert np.max(np.abs(r["u_new"] - ref["xi_star"])) <= 1e-6
+        with pytest.raises(V.VpmError) as e:
+            p.poll(t)                                         # the ticket was released
+        assert e.value.code == V.ENOTFOUND
+        p.drop_state(sid)
+    finally:
+        p.close()
