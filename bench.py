@@ -1,13 +1,22 @@
 """Benchmark of the rollout hot path on one MI355X.
 
 One step = one MPPI iteration of the planner's hot path on one batch:
-``vpm_rollout_batch`` (K rollouts x H steps of the VPM-glider model, terminal
-cost) followed by ``mppi_weights`` (softmin weights and the control update).
-Inputs are resident in HBM before the timed region starts.
+``vpm_rollout_batch`` (K rollouts x H steps of the VPM-glider model and the
+terminal cost) followed by ``mppi_weights`` (softmin weights and the control
+update). Inputs are resident in HBM before the timed region starts.
 
-Default workload: K = 1024 rollouts, H = 200 steps at dt = 2.5 ms, 32 bound
-vortices, one disturbance pair, FP32 with compensated sums (FP64 surface
-solve). Prints one JSON line.
+Workloads (``--workload``):
+  realtime (default)  K=1024, H=200, dt=2.5 ms, 32 bound vortices, one
+                      disturbance pair, FP32 with compensated sums
+  plain               K=32, H=100, dt=5 ms, 16 bound vortices, merging above
+                      200, FP64
+  uneven              K=4096, H=100, initial wakes of 50..4000 vortices each
+                      (log-uniform), FP32, planned persistent class kernels
+  stress              K=8192, H=150, 16376-vortex Lamb-Oseen field, 64 bound
+                      vortices, merging above 16384, FP32 (streamed wakes)
+The default run also replays the first requests of the serving trace through
+the replanning service (8 slots) and through the plain one-at-a-time path,
+reporting p50/p99 latency and rollouts/s for both. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,41 +34,152 @@ if ROOT not in sys.path:
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 FLOP_REG, FLOP_SING = 13, 11  # algorithmic FLOP per regularised / singular pair
+METRIC = "vortex pair-interactions/s, MPPI rollouts/s, p50/p99 replan latency vs plain"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp32c", "fp64"], default="fp32c")
-    ap.add_argument("--K", type=int, default=1024)
-    ap.add_argument("--H", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress"],
+                    default="realtime")
+    ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256, help="rollouts timed on the oracle")
+    ap.add_argument("--serving-requests", type=int, default=None,
+                    help="requests of the serving trace to replay (0: skip)")
+    ap.add_argument("--slice", type=int, default=None,
+                    help="launch the batch in slices of this many rollouts, reporting each "
+                         "finished slice (default: whole batch; 1024 for stress)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(wl, n_sample):
-    """The FP64 oracle on a bounded sample of the same workload, all host cores."""
-    from oracle import oracle as O
-    O.build(force=False)
-    idx = np.linspace(0, wl.K - 1, n_sample).astype(np.int64)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    O.rollout_batch(wl.params, wl.K, wl.H, wl.dt, wl.g0, wl.gb0, wl.field_off, wl.field_of,
-                    wl.wx, wl.wz, wl.wg, wl.pairs, wl.u, wl.x_goal, wl.q_diag,
-                    rollouts=idx, n_threads=threads)
-    dt = time.perf_counter() - t0
+def make_workload(name):
     from paper_2509_16079_amd import workloads as W
-    pairs = sum(sum(W.pair_count(wl.n0[k], wl.H, wl.params["n_bound"],
-                                 n_wake_max=wl.params["n_wake_max"])) for k in idx)
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads,
-            "kind": "oracle", "rollouts_per_s": n_sample / dt, "seconds": dt,
-            "sample": "%d of the %d rollouts (evenly spaced indices), full horizon H=%d, "
-                      "OpenMP over rollouts" % (n_sample, wl.K, wl.H)}
+    if name == "realtime":
+        wl = W.realtime()
+        desc = ("realtime FP32-vs-FP64 batch: K=1024 rollouts, H=200 steps, dt=2.5 ms, "
+                "N_b=32, N_w<=402, one disturbance pair")
+        return wl, desc, "fp32c", (10, 3)
+    if name == "plain":
+        wl = W.plain_single_plan()
+        desc = ("plain single plan: K=32 rollouts, H=100 steps, dt=5 ms, N_b=16, "
+                "N_w,max=200, one disturbance pair")
+        return wl, desc, "fp64", (20, 3)
+    if name == "uneven":
+        wl = W.uneven_batch()
+        desc = ("uneven batch: K=4096 rollouts, H=100 steps, dt=5 ms, N_b=32, initial wakes "
+                "log-uniform in [50, 4000] vortices, one planned persistent launch")
+        return wl, desc, "fp32c", (3, 1)
+    wl = W.large_stress()
+    desc = ("large stress: K=8192 rollouts, H=150 steps, dt=5 ms, N_b=64, 16376-vortex "
+            "Lamb-Oseen field + 4 pairs, N_w,max=16384")
+    return wl, desc, "fp32c", (1, 0)
+
+
+def work_counts(wl):
+    from paper_2509_16079_amd import workloads as W
+    cache = {}
+    n_reg = n_sing = 0
+    for n in wl.n0:
+        n = int(n)
+        if n not in cache:
+            cache[n] = W.pair_count(n, wl.H, wl.params["n_bound"],
+                                    n_wake_max=wl.params["n_wake_max"])
+        r, s = cache[n]
+        n_reg += r
+        n_sing += s
+    return n_reg, n_sing
+
+
+def cpu_baseline(name, wl):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload, all host cores (OpenMP over rollouts)."""
+    from oracle import oracle as O
+    from paper_2509_16079_amd import workloads as W
+    O.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    H = wl.H
+    if name == "realtime":
+        idx = np.linspace(0, wl.K - 1, 256).astype(np.int64)
+        what = "256 of the 1024 rollouts (evenly spaced), full horizon H=200"
+    elif name == "plain":
+        idx = np.arange(wl.K)
+        what = "all 32 rollouts, full horizon H=100"
+    elif name == "uneven":
+        order = np.argsort(wl.n0)
+        idx = order[np.linspace(0, wl.K - 1, 64).astype(np.int64)]
+        what = "64 rollouts stratified by initial wake size, full horizon H=100"
+    else:
+        idx = np.arange(16)
+        H = 1
+        what = "16 rollouts, first step only (1 of 150), per-pair rate"
+    sub = wl.subset(idx)
+    if H != wl.H:
+        from dataclasses import replace
+        sub = replace(sub, H=H, u_mean=sub.u_mean[:H], u_eps=sub.u_eps[:, :H])
+    t0 = time.perf_counter()
+    O.rollout_batch(sub.params, sub.K, sub.H, sub.dt, sub.g0, sub.gb0, sub.field_off,
+                    sub.field_of, sub.wx, sub.wz, sub.wg, sub.pairs, sub.u, sub.x_goal,
+                    sub.q_diag, n_threads=threads)
+    dt = time.perf_counter() - t0
+    pairs = sum(sum(W.pair_count(int(n), H, sub.params["n_bound"],
+                                 n_wake_max=sub.params["n_wake_max"])) for n in sub.n0)
+    out = {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads,
+           "kind": "oracle", "seconds": dt, "sample": what + "; OpenMP over rollouts"}
+    if H == wl.H:
+        out["rollouts_per_s"] = len(idx) / dt
+    return out
+
+
+def serving(n_requests):
+    """Replay the first requests of the serving trace (Poisson arrivals at
+    100 req/s, K~U{256..2048}, H~U{50..200}, 16 resident states of
+    500..6000 vortices) through the service and through the plain path."""
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    params, states, reqs = W.serving_trace()
+    reqs = reqs[:n_requests]
+    eps = [W.request_eps(r) for r in reqs]
+    dt = float(W.f32(0.005))
+    g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
+
+    def replay(slots):
+        p = V.Planner(max_slots=slots, budget_bytes=64 << 30)
+        try:
+            sids = [p.put_state(*s, g0, np.zeros(32)) for s in states]
+            # warm-up (not timed): one small request per resident state
+            for sid in sids:
+                p.poll(p.submit(sid, params, np.zeros(4), np.zeros((64, 4)), dt))
+            t_start = time.perf_counter()
+            tickets = []
+            for r, e in zip(reqs, eps):
+                delay = t_start + r.t_arrive - reqs[0].t_arrive - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(p.submit(sids[r.state], params, np.zeros(r.H), e, dt))
+            res = [p.poll(t) for t in tickets]
+        finally:
+            p.close()
+        assert all(x["status"] == 0 for x in res)
+        lat = np.array([x["t_done_us"] - x["t_arrive_us"] for x in res]) * 1e-3
+        span = (max(x["t_done_us"] for x in res) - min(x["t_arrive_us"] for x in res)) * 1e-6
+        rollouts = sum(r.K for r in reqs)
+        pairs = sum(x["pairs"] for x in res)
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "rollouts_per_s": rollouts / span, "pair_interactions_per_s": pairs / span,
+                "makespan_s": span}
+
+    served = replay(8)
+    plain = replay(1)
+    return {"requests": len(reqs), "trace": "first %d requests of the seeded 100 req/s "
+            "trace (K~U{256..2048}, H~U{50..200}, resident states of 500..6000 vortices)"
+            % len(reqs),
+            "served_8_slots": served, "plain_one_at_a_time": plain,
+            "p99_speedup": plain["p99_ms"] / served["p99_ms"],
+            "rollouts_speedup": served["rollouts_per_s"] / plain["rollouts_per_s"]}
 
 
 def main():
@@ -72,27 +192,43 @@ def main():
     import torch
 
     from paper_2509_16079_amd import vpm as V
-    from paper_2509_16079_amd import workloads as W
 
-    prec = V.FP32C if args.precision == "fp32c" else V.FP64
-    wl = W.realtime(K=args.K, H=args.H)
+    wl, desc, prec_name, (steps_d, warm_d) = make_workload(args.workload)
+    steps = steps_d if args.steps is None else args.steps
+    warmup = warm_d if args.warmup is None else args.warmup
+    prec_name = args.precision or prec_name
+    prec = V.FP32C if prec_name == "fp32c" else V.FP64
     ctx = V.Context(0)
     db = V.DeviceBatch(wl)
     out = V.DeviceOutputs(db, pair_count=True)
     stream = torch.cuda.current_stream()
-    reg_sing = [W.pair_count(n, wl.H, wl.params["n_bound"], n_wake_max=wl.params["n_wake_max"])
-                for n in wl.n0]
-    n_reg = sum(r for r, _ in reg_sing)
-    n_sing = sum(s for _, s in reg_sing)
+    n_reg, n_sing = work_counts(wl)
     pairs_per_step = n_reg + n_sing
     flop_per_launch = FLOP_REG * n_reg + FLOP_SING * n_sing
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        ctx.rollout(wl.params, db, out, prec, stream)
-        if ev is not None:
-            ev[1].record(stream)
+    slice_k = args.slice if args.slice is not None else (1024 if args.workload == "stress" else 0)
+    kernel_ms = []
+
+    def step(timed=False):
+        if slice_k <= 0 or slice_k >= wl.K:
+            if timed:
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev[0].record(stream)
+            ctx.rollout(wl.params, db, out, prec, stream)
+            if timed:
+                ev[1].record(stream)
+                kernel_ms.append(ev)
+        else:
+            for k0 in range(0, wl.K, slice_k):
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev[0].record(stream)
+                ctx.rollout(wl.params, db, out, prec, stream, k0, min(wl.K, k0 + slice_k))
+                ev[1].record(stream)
+                ev[1].synchronize()
+                if timed:
+                    kernel_ms.append(ev)
+                print("slice %d..%d done" % (k0, min(wl.K, k0 + slice_k)), file=sys.stderr,
+                      flush=True)
         ctx.mppi(out.cost, wl.lam, db.u_mean, db.u_eps, stream)
 
     if args.calibrate_copy_mb > 0:
@@ -101,50 +237,50 @@ def main():
         dst = src.clone()
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    assert int(out.pair_count.sum().item()) == pairs_per_step
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
+    for i in range(steps):
+        step(timed=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in evs]
-    kern_avg = float(np.mean(kern_ms))
-    ms = 1e3 * wall / args.steps
+    assert int(out.pair_count.sum().item()) == pairs_per_step
+    kern_avg = float(sum(a.elapsed_time(b) for a, b in kernel_ms) / steps)
+    ms = 1e3 * wall / steps
     status = out.status.cpu().numpy()
     achieved = flop_per_launch / (kern_avg * 1e-3) / 1e12
     line = {
-        "metric": "vortex pair-interactions/s, MPPI rollouts/s, p50/p99 replan latency vs plain",
+        "metric": METRIC,
         "value": pairs_per_step / (ms * 1e-3),
         "unit": "pair-interactions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if prec == V.FP32C else "f64",
         "data": "synthetic",
-        "config": {"workload": "realtime FP32-vs-FP64 batch: K=%d rollouts, H=%d steps, "
-                               "dt=2.5 ms, N_b=32, N_w<=%d, one disturbance pair"
-                               % (wl.K, wl.H, 2 + 2 * wl.H),
-                   "K": wl.K, "H": wl.H, "n_bound": 32, "precision": args.precision},
+        "config": {"workload": desc, "K": wl.K, "H": wl.H, "n_bound": wl.params["n_bound"],
+                   "precision": prec_name},
         "rollouts_per_s": wl.K / (ms * 1e-3),
         "pairs_per_step": pairs_per_step,
         "rollout_kernel_ms": kern_avg,
+        "launch_slices": 1 if slice_k <= 0 or slice_k >= wl.K else -(-wl.K // slice_k),
         "nonfinite_rollouts": int(np.sum(status != 0)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
     ctx.close()
+    n_serve = args.serving_requests
+    if n_serve is None:
+        n_serve = 16 if args.workload == "realtime" else 0
+    if n_serve > 0:
+        line["serving"] = serving(n_serve)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, wl)
     print(json.dumps(line), flush=True)
 
 

@@ -172,8 +172,17 @@ VPM_API int vpm_validate_batch(const vpm_params *params, const vpm_batch_in *in,
  * and decay (Eq. 17), merging of the two oldest vortices above N_w,max, the
  * disturbance termination test (Sec. V) and the explicit Euler glider step.
  * Errors: VPM_EINVAL (bad sizes, NULL required pointers, shed_mode other
- * than BOTH), VPM_ECAPACITY (max_wake0 + 2H beyond the kernel's LDS limit),
- * VPM_ESINGULAR, VPM_EDEVICE. */
+ * than BOTH; or, during stream capture, a first call that would have to
+ * build a plate inverse or grow a context buffer), VPM_ECAPACITY
+ * (max_wake0 + 2H beyond the LDS limit when VPM_PATH_LDS is forced),
+ * VPM_ENOMEM, VPM_ESINGULAR, VPM_EDEVICE.
+ * Graph capture: the call may be captured into a HIP graph once an eager
+ * call with the same geometry and no smaller sizes has run on this context;
+ * it then allocates nothing, records no memset, and forks its class kernels
+ * onto the context's side streams and joins them back. A replayed graph
+ * reuses the context's workspace without the cross-stream ordering that
+ * eager calls get, so the caller must not run it concurrently with other
+ * calls on the same context. */
 VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
                               const vpm_batch_in *in, vpm_batch_out *out,
                               void *stream);

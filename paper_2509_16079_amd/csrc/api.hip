@@ -45,6 +45,12 @@ int check_params(const vpm_params *p) {
 }
 
 }  // namespace
+
+bool stream_capturing(hipStream_t stream) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 }  // namespace vpm
 
 using vpm::fail;
@@ -154,7 +160,8 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
   if (rc != VPM_OK) return rc;
   VPM_HIP_TRY(hipSetDevice(ctx->device));
   const double *kinv = nullptr;
-  rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_BOTH, &kinv);
+  rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_BOTH, &kinv,
+                                 vpm::stream_capturing(static_cast<hipStream_t>(stream)));
   if (rc != VPM_OK) return rc;
   return vpm::launch_rollout(ctx, params, in, out, kinv,
                              static_cast<hipStream_t>(stream));
@@ -177,7 +184,8 @@ VPM_API int vpm_plate_solve(vpm_ctx *ctx, const vpm_params *params, int32_t B,
     return fail(VPM_EINVAL, "a pointer is NULL");
   VPM_HIP_TRY(hipSetDevice(ctx->device));
   const double *kinv = nullptr;
-  rc = vpm::plate_inverse_device(ctx, params, shed_mode, &kinv);
+  rc = vpm::plate_inverse_device(ctx, params, shed_mode, &kinv,
+                                 vpm::stream_capturing(static_cast<hipStream_t>(stream)));
   if (rc != VPM_OK) return rc;
   return vpm::launch_plate_solve(params, B, pose, vw_c, sum_gw, shed_mode, kinv,
                                  gamma_s, static_cast<hipStream_t>(stream));

@@ -88,7 +88,7 @@ int plate_inverse_T(int nb, double chord, double shed_frac, double r_core,
 }
 
 int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
-                         const double **out) {
+                         const double **out, bool capturing) {
   PlateKey key{p->n_bound, mode, p->chord, p->shed_frac, p->r_core};
   std::lock_guard<std::mutex> lock(ctx->mu);
   auto it = ctx->plate_cache.find(key);
@@ -96,6 +96,9 @@ int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
     *out = it->second;
     return VPM_OK;
   }
+  if (capturing)
+    return fail(VPM_EINVAL, "the plate inverse of this geometry must be built by an "
+                            "eager call before graph capture");
   std::vector<double> inv_t;
   int rc = plate_inverse_T(p->n_bound, p->chord, p->shed_frac, p->r_core, mode,
                            inv_t);

@@ -868,9 +868,14 @@ int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
 }
 
 // Grow a context buffer to `bytes` (device-synchronises before freeing a
-// smaller one).
-int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what) {
+// smaller one). Under graph capture nothing may be allocated: the buffer must
+// already have been grown by an eager call of the same shape.
+int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what,
+                  bool capturing) {
   if (*have >= bytes) return VPM_OK;
+  if (capturing)
+    return fail(VPM_EINVAL, std::string("the ") + what +
+                                " must be sized by an eager call before graph capture");
   if (*buf) {
     VPM_HIP_TRY(hipDeviceSynchronize());
     VPM_HIP_TRY(hipFree(*buf));
@@ -887,7 +892,7 @@ int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what) {
 
 template <typename R, int TMAX, int NW>
 int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
-                  hipStream_t stream) {
+                  hipStream_t stream, bool capturing) {
   const int lds = stream_layout<R>(a.nb, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
@@ -895,7 +900,7 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
-  rc = ensure_buffer(&ctx->ws, &ctx->ws_bytes, slot * grid, "streaming workspace");
+  rc = ensure_buffer(&ctx->ws, &ctx->ws_bytes, slot * grid, "streaming workspace", capturing);
   if (rc != VPM_OK) return rc;
   a.ws_src = ctx->ws;
   a.ws_vel = static_cast<char *>(ctx->ws) +
@@ -915,15 +920,20 @@ int lds_capacity(int nb, int S, int nw, int tmax, size_t bytes) {
 // One batch in a given precision. Uniform batches (one field) run one
 // rollout per workgroup on the caller's stream. Uneven batches are planned
 // on the device and run as up to three persistent class kernels on forked
-// streams, joined back into the caller's stream.
+// streams, joined back into the caller's stream. Calls that use the
+// context's workspace are ordered by an event; while the caller's stream is
+// being captured into a graph that ordering is the caller's (replays of a
+// graph and other calls on the same context must not overlap).
 template <typename R, int TMAX_S, int MINW_S, int TMAX_L, int TMAX_X, int NW_X>
 int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  VPM_HIP_TRY(hipStreamIsCapturing(stream, &cap_status));
+  const bool capturing = cap_status != hipStreamCaptureStatusNone;
   // FP32 takes 16-wave large-class workgroups (128 VGPRs each), FP64 8
   constexpr int kNwSmall = 4, kNwLarge = sizeof(R) == 4 ? 16 : 8;
   const int cap = a.cap;  // max_wake0 + 2H
   const int cap_small = lds_capacity<R>(a.nb, a.S, kNwSmall, TMAX_S, ctx->max_lds / 4);
   const int cap_large = lds_capacity<R>(a.nb, a.S, kNwLarge, TMAX_L, ctx->max_lds);
-  const int cap_lds_small_max = lds_capacity<R>(a.nb, a.S, kNwSmall, TMAX_S, ctx->max_lds);
   const Queue none{nullptr, nullptr, nullptr, 0};
   const bool stream_only = path == VPM_PATH_STREAM;
   if (a.n_fields == 1 || path == VPM_PATH_LDS || stream_only) {
@@ -931,26 +941,28 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
       return launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream);
     if (!stream_only && cap <= cap_large)
       return launch_lds<R, TMAX_L, 1, kNwLarge>(ctx, a, cap, a.K, none, stream);
-    if (!stream_only && cap <= cap_lds_small_max)
-      return launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream);
     if (path == VPM_PATH_LDS)
       return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
                                      " does not fit the LDS-resident kernel");
     std::lock_guard<std::mutex> lock(ctx->ws_mu);
-    if (ctx->ws_event_valid) VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
+    if (ctx->ws_event_valid && !capturing)
+      VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
     const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
-    int rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, none, stream);
+    int rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, none, stream, capturing);
     if (rc != VPM_OK) return rc;
-    VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
-    ctx->ws_event_valid = true;
+    if (!capturing) {
+      VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
+      ctx->ws_event_valid = true;
+    }
     return VPM_OK;
   }
 
   // uneven batch: plan, then the class kernels
   std::lock_guard<std::mutex> lock(ctx->ws_mu);
-  if (ctx->ws_event_valid) VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
+  if (ctx->ws_event_valid && !capturing)
+    VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
   const size_t plan_bytes = (size_t)a.K * sizeof(int32_t) + 64;
-  int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan");
+  int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan", capturing);
   if (rc != VPM_OK) return rc;
   int2 *range = static_cast<int2 *>(ctx->plan);
   int32_t *next = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->plan) + 32);
@@ -967,7 +979,7 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
     hipStream_t s = ctx->side[0];
     VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
     const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
-    rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, Queue{list, next, range, 0}, s);
+    rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, Queue{list, next, range, 0}, s, capturing);
     if (rc != VPM_OK) return rc;
     VPM_HIP_TRY(hipEventRecord(ctx->join_event[0], s));
     joins[n_join++] = ctx->join_event[0];
@@ -995,15 +1007,17 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
     joins[n_join++] = ctx->join_event[2];
   }
   for (int i = 0; i < n_join; ++i) VPM_HIP_TRY(hipStreamWaitEvent(stream, joins[i], 0));
-  VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
-  ctx->ws_event_valid = true;
+  if (!capturing) {
+    VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
+    ctx->ws_event_valid = true;
+  }
   return VPM_OK;
 }
 
 }  // namespace
 
 int lds_resident_capacity(int nb) {
-  return lds_capacity<float>(nb, nb + 2, 4, 4, 163840);
+  return lds_capacity<float>(nb, nb + 2, 16, 2, 163840);
 }
 
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,

@@ -79,9 +79,13 @@ struct vpm_ctx {
 
 namespace vpm {
 
-// Device inverse for a plate (cached in the context).
+// Device inverse for a plate (cached in the context; building one is
+// refused while the caller's stream is captured into a graph).
 int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
-                         const double **out);
+                         const double **out, bool capturing);
+
+// True if `stream` is being captured into a graph.
+bool stream_capturing(hipStream_t stream);
 
 // Largest FP32 wake capacity (N_0 + 2H) the LDS-resident kernel holds on a
 // gfx950 workgroup (160 KB of LDS); larger wakes take the streaming kernel.

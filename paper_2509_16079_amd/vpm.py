@@ -100,8 +100,10 @@ def pair_count(n0, H, n_bound, n_wake_max):
     return int(lib().vpm_pair_count(int(n0), int(H), int(n_bound), int(n_wake_max)))
 
 
-def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+def _ptr(t, offset_elems=0):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr() + offset_elems * t.element_size())
 
 
 def _stream_handle(stream):
@@ -133,15 +135,18 @@ class DeviceBatch:
         sizes = np.diff(wl.field_off)
         self.max_wake0 = int(sizes.max()) if sizes.size else 0
 
-    def batch_in(self) -> BatchIn:
+    def batch_in(self, k0=0, k1=None) -> BatchIn:
+        """The ABI input struct for rollouts [k0, k1) of this batch."""
+        k1 = self.K if k1 is None else k1
+        nb = self.gb0.shape[1]
         b = BatchIn()
-        b.K, b.H, b.dt = self.K, self.H, self.dt
+        b.K, b.H, b.dt = k1 - k0, self.H, self.dt
         b.n_fields, b.max_wake0, b.n_pairs = self.n_fields, self.max_wake0, self.n_pairs
-        b.g0, b.gb0, b.field_off, b.field_of = (_ptr(self.g0), _ptr(self.gb0),
-                                                _ptr(self.field_off), _ptr(self.field_of))
+        b.g0, b.gb0 = _ptr(self.g0, 7 * k0), _ptr(self.gb0, nb * k0)
+        b.field_off, b.field_of = _ptr(self.field_off), _ptr(self.field_of, k0)
         b.wx, b.wz, b.wg = _ptr(self.wx), _ptr(self.wz), _ptr(self.wg)
-        b.pairs = _ptr(self.pairs)
-        b.u_mean, b.u_eps = _ptr(self.u_mean), _ptr(self.u_eps)
+        b.pairs = _ptr(self.pairs, 2 * self.n_pairs * k0)
+        b.u_mean, b.u_eps = _ptr(self.u_mean), _ptr(self.u_eps, self.H * k0)
         for i in range(7):
             b.x_goal[i] = float(self.wl.x_goal[i])
             b.q_diag[i] = float(self.wl.q_diag[i])
@@ -181,10 +186,17 @@ class DeviceOutputs:
                 self.vel_last = torch.empty((tot, 2), **f64)
                 self.n_vel_last = torch.empty(K, dtype=torch.int32, device=device)
 
-    def batch_out(self) -> BatchOut:
+    def batch_out(self, k0=0, k1=None) -> BatchOut:
+        """The ABI output struct for rollouts [k0, k1) (per-rollout arrays
+        only; the wake block is passed for whole batches)."""
         o = BatchOut()
-        for name, _ in BatchOut._fields_:
-            setattr(o, name, _ptr(getattr(self, name)))
+        if k0 == 0 and k1 is None:
+            for name, _ in BatchOut._fields_:
+                setattr(o, name, _ptr(getattr(self, name)))
+            return o
+        per = dict(g_final=7, cost=1, status=1, pair_count=1)
+        for name, width in per.items():
+            setattr(o, name, _ptr(getattr(self, name), width * k0))
         return o
 
     def to_numpy(self) -> dict:
@@ -224,10 +236,14 @@ class Context:
             pass
 
     def rollout(self, params: dict, db: DeviceBatch, out: DeviceOutputs, precision=FP32C,
-                stream=None):
-        """Enqueue ``vpm_rollout_batch`` on ``stream`` (default: torch's current)."""
+                stream=None, k0=0, k1=None):
+        """Enqueue ``vpm_rollout_batch`` on ``stream`` (default: torch's current)
+        for rollouts [k0, k1) of the batch (default: all)."""
         p = make_params(params, precision)
-        bi, bo = db.batch_in(), out.batch_out()
+        if k0 == 0 and k1 is None:
+            bi, bo = db.batch_in(), out.batch_out()
+        else:
+            bi, bo = db.batch_in(k0, k1), out.batch_out(k0, k1)
         check(lib().vpm_rollout_batch(self.h, C.byref(p), C.byref(bi), C.byref(bo),
                                       _stream_handle(stream)), "vpm_rollout_batch")
         return out
