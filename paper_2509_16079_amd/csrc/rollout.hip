@@ -577,6 +577,27 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
 }
 
+// Tail of r < 64 targets: lane l takes target c0 + l mod r and the part
+// l / r of g = 64 / r equal parts of this wave's sources, so g r lanes work
+// instead of r. The partials land where a T = 1 chunk puts them, lane l at
+// red[wave 64 + l], and are added per target over waves, then parts.
+template <typename R, int NW>
+__device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
+                                const typename SrcOf<R>::type *src, Vec2<R> *red,
+                                int c0, int NT, int head, int s_lo, int s_hi,
+                                int r, int lane, int wave) {
+  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  const int g = 64 / r, t = lane % r, q = lane / r;
+  R tx[1], tz[1], sx[1] = {R(0)}, sz[1] = {R(0)}, cx[1] = {R(0)}, cz[1] = {R(0)};
+  target_pos(a, sh, src, c0 + t, NT, head, tx[0], tz[0]);
+  if (q < g) {
+    const int len = s_hi - s_lo;
+    accumulate<R, 1>(src, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
+                     sx, sz, cx, cz);
+  }
+  red[wave * 64 + lane] = Vec2<R>{sx[0] + cx[0], sz[0] + cz[0]};
+}
+
 // LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
@@ -617,20 +638,28 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         const int rem = NT - c0;
         int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
         while (T > 1 && 64 * T > rem) T >>= 1;
-        switch (T) {
-          case 1: lds_pass_a_chunk<R, 1, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-          case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-          default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+        const int tail = rem < 32 ? rem : 0;  // tails of 32..63 keep a lane each
+        if (tail) {
+          lds_pass_a_tail<R, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
+        } else {
+          switch (T) {
+            case 1: lds_pass_a_chunk<R, 1, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+          }
         }
         __syncthreads();
         const int span = 64 * T;
+        const int parts = tail ? 64 / tail : 1;
         for (int t = tid; t < span && c0 + t < NT; t += kThr) {
           double vx = 0.0, vz = 0.0;
 #pragma unroll
           for (int w = 0; w < NW; ++w) {
-            const Vec2<R> r = red[w * span + t];
-            vx += double(r.x);
-            vz += double(r.z);
+            for (int q = 0; q < parts; ++q) {
+              const Vec2<R> r = red[w * span + q * tail + t];
+              vx += double(r.x);
+              vz += double(r.z);
+            }
           }
           const int tt = c0 + t;
           if (tt < n_surf)
