@@ -1,0 +1,70 @@
+"""Test infrastructure: run rollout cases through the emulated library and
+print one JSON line per (case, precision) with the errors against the
+oracle. Runs in its own process (the emulated library exports the same
+symbols as the product library)."""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+os.environ.setdefault("EMU_N_CU", "4")
+
+from paper_2509_16079_amd import vpm as V  # noqa: E402
+from paper_2509_16079_amd import workloads as W  # noqa: E402
+from tests.parity import rel_l2, run_oracle, wake_segments  # noqa: E402
+
+V.LIB_PATH = os.path.join(HERE, "_build", "libvpm_emu.so")
+
+
+class _Stream:
+    cuda_stream = 0
+
+
+def cases():
+    return {
+        # empty initial wake over several steps, N_b = 16
+        "empty": lambda: W.workload_from_state(
+            "empty", W.make_params(16), (np.zeros(0), np.zeros(0), np.zeros(0)), K=3, H=5,
+            eps=W.f32(np.full((3, 5), 0.1))),
+        # realtime batch, a few steps (surface chunk + tail, wake tasks)
+        "realtime": lambda: W.realtime(K=2, H=6),
+        # N_b = 64: a system of 66 rows (two rows per lane in the solve)
+        "nb64": lambda: W.workload_from_state(
+            "nb64", W.make_params(64), W.random_field(np.random.default_rng(5), 300), K=2, H=4,
+            eps=W.f32(np.full((2, 4), 0.05))),
+        # uneven counts 1..700: planned small class, ragged tails of every size
+        "uneven": lambda: W.uneven_batch(K=6, H=3, n_min=1, n_max=700),
+        # counts 1100..7000: large class with 128-target tasks and streamed rollouts
+        "large": lambda: W.uneven_batch(K=5, H=2, n_min=1100, n_max=7000),
+    }
+
+
+def main(names):
+    ctx = V.Context(0)
+    for name in names:
+        wl = cases()[name]()
+        o = run_oracle(wl, traj=True, final_wake=True, gamma_s=True)
+        for prec in (V.FP32C, V.FP64):
+            db = V.DeviceBatch(wl, device="cpu")
+            out = V.DeviceOutputs(db, device="cpu", traj=True, final_wake=True, gamma_s=True)
+            ctx.rollout(wl.params, db, out, prec, stream=_Stream())
+            g = out.to_numpy()
+            wake = max((rel_l2(a, b) for k in range(wl.K)
+                        for a, b in zip(wake_segments(g, k), wake_segments(o, k))), default=0.0)
+            print(json.dumps({
+                "case": name, "prec": prec,
+                "traj": rel_l2(g["traj"], o["traj"]),
+                "gamma_s": rel_l2(g["gamma_s"], o["gamma_s"]),
+                "g_final": rel_l2(g["g_final"], o["g_final"]),
+                "wake": wake,
+                "n_final_equal": bool(np.array_equal(g["n_final"], o["n_final"])),
+                "status": g["status"].tolist()}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,45 @@
+"""CPU: the rollout kernels' logic, compiled for the CPU against an emulation
+of the HIP subset they use (tests/emu), against the FP64 oracle: indexing,
+task partitioning, synchronisation (a deadlock fails the test by timeout)
+and the results to the GPU parity tolerances, over horizons short enough
+that the conditioning of the flow does not enter. It does not replace the
+GPU tests (it does not see the compiler's code generation)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from tests.parity import TOL
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(HERE, "emu")
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.fixture(scope="module")
+def emu_lib():
+    r = subprocess.run([sys.executable, os.path.join(EMU, "build.py")], capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return r.stdout.strip()
+
+
+@pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large"])
+def test_emulated_kernels_match_oracle(emu_lib, case):
+    try:
+        r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), case],
+                           capture_output=True, text=True, timeout=300, cwd=ROOT)
+    except subprocess.TimeoutExpired:
+        pytest.fail("emulated kernels did not finish (deadlock?) on case " + case)
+    assert r.returncode == 0, r.stderr[-3000:]
+    rows = [json.loads(x) for x in r.stdout.splitlines() if x.startswith("{")]
+    assert len(rows) == 2
+    for row in rows:
+        tol = TOL[row["prec"]]
+        assert all(s == 0 for s in row["status"]), row
+        assert row["n_final_equal"], row
+        for key in ("traj", "gamma_s", "g_final"):
+            assert row[key] <= tol, (key, row)
+        assert row["wake"] <= 10 * tol, row
