@@ -60,6 +60,7 @@ template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
 struct KArgs {
   int K, H, nb, S, n_wake_max, max_wake0, n_pairs, cap, n_fields;
   double dt, chord, shed_frac, r_core, decay, rho, span, grav, mass, inertia;
+  double inv_dt, inv_lb, inv_mass, inv_inertia;  // host reciprocals
   double l_body, l_wing, l_elev, s_elev;
   double x_goal[7], q_diag[7];
   const double *g0, *gb0, *wx, *wz, *wg, *u_mean, *u_eps, *kinv_t;
@@ -78,6 +79,7 @@ struct KArgs {
 template <typename R> struct Shared {
   R g[7], gn[7];
   R le[2], et[2], en[2], xw[2], xwd[2], lev[2], tev[2];
+  R ct, st;  // cos and sin of the pitch at the start of the step
   R bpos[kMaxBound][2];
   R bgam[kMaxBound];
   R shed_g[2];
@@ -85,6 +87,7 @@ template <typename R> struct Shared {
   double bvec[kMaxBound + 2];
   int head, n_w, status;
   int claimed;  // rollout claimed from the work queue
+  int slot;     // issue-priority slot of this workgroup (see rotate_priority)
   int pa[kMaxPairs], pb[kMaxPairs];
   long long pairs;
 };
@@ -210,7 +213,8 @@ __device__ inline void target_pos(const KArgs &a, const Shared<R> &sh,
 __device__ inline bool clip_slab(double p0, double d, double lo, double hi,
                                  double &u0, double &u1) {
   if (d == 0.0) return p0 >= lo && p0 <= hi;
-  double ta = (lo - p0) / d, tb = (hi - p0) / d;
+  const double inv = 1.0 / d;
+  double ta = (lo - p0) * inv, tb = (hi - p0) * inv;
   if (ta > tb) {
     double t = ta;
     ta = tb;
@@ -238,6 +242,8 @@ __device__ void geometry(const KArgs &a, Shared<R> &sh) {
   const R th = sh.g[2], thd = sh.g[6], lw = R(a.l_wing);
   const R ct = cos(th), st = sin(th);
   const R hc = R(0.5 * a.chord), ds = R(a.shed_frac * a.chord);
+  sh.ct = ct;
+  sh.st = st;
   sh.xw[0] = sh.g[0] - lw * ct;
   sh.xw[1] = sh.g[1] - lw * st;
   sh.xwd[0] = sh.g[4] + lw * thd * st;
@@ -347,6 +353,8 @@ __device__ __forceinline__ void solve_section(
     const double vz = vw.y - xwdz - thd * (px - xwx);
     return -(vx * enx + vz * enz);
   };
+  // b goes through LDS (broadcast reads cost no VALU issue slots); the
+  // inverse and b are read 8 entries at a time
   if (lane < S) sh.bvec[lane] = rhs(lane);
   if (lane + 64 < S) sh.bvec[lane + 64] = rhs(lane + 64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -355,11 +363,23 @@ __device__ __forceinline__ void solve_section(
   // Gamma_S = K^-1 b (Eq. 11): lane i owns rows i and i + 64
   double gam0 = 0.0, gam1 = 0.0;
   const int i0 = lane < S ? lane : 0, i1 = lane + 64 < S ? lane + 64 : 0;
-#pragma unroll 8
-  for (int j = 0; j < S; ++j) {
-    const double bj = sh.bvec[j];
-    gam0 += kinv[j * S + i0] * bj;
-    gam1 += kinv[j * S + i1] * bj;
+  for (int j0 = 0; j0 < S; j0 += 8) {
+    double kv[8], bj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = j0 + q < S ? j0 + q : S - 1;
+      kv[q] = kinv[j * S + i0];
+      bj[q] = j0 + q < S ? sh.bvec[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) gam0 += kv[q] * bj[q];
+    if (S > 64) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = j0 + q < S ? j0 + q : S - 1;
+        gam1 += kinv[j * S + i1] * bj[q];
+      }
+    }
   }
   auto row = [&](int r) -> double {
     return r < 64 ? __shfl(gam0, r, 64) : __shfl(gam1, r - 64, 64);
@@ -384,9 +404,10 @@ __device__ __forceinline__ void solve_section(
   const double vtz = vb.y - xwdz - thd * (bx - xwx);
   const double qt = vtx * etx + vtz * etz;
   const double arm = 0.5 * a.chord - sj;
-  const double local = (gbj / lb) * qt + glev / dt;
-  const double tf = on ? local + (nb - lane) * dgb / dt : 0.0;
-  const double tm = on ? arm * local - 0.5 * (nb - lane) * lane * lb * dgb / dt : 0.0;
+  const double inv_dt = a.inv_dt;
+  const double local = gbj * a.inv_lb * qt + glev * inv_dt;
+  const double tf = on ? local + (nb - lane) * dgb * inv_dt : 0.0;
+  const double tm = on ? arm * local - 0.5 * (nb - lane) * lane * lb * dgb * inv_dt : 0.0;
   const double sdp = a.rho * wave_sum(tf);
   const double sarm = a.rho * wave_sum(tm);
   if (on) {
@@ -403,7 +424,7 @@ __device__ __forceinline__ void solve_section(
     const R xd = sh.g[4], zd = sh.g[5], thr = sh.g[6];
     const R u = R(a.u_mean[n] + a.u_eps[(size_t)k * a.H + n]);
     const R l = R(a.l_body), le = R(a.l_elev);
-    const R ct = cos(th), st = sin(th), ctp = cos(th + ph), stp = sin(th + ph);
+    const R ct = sh.ct, st = sh.st, ctp = cos(th + ph), stp = sin(th + ph);
     const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
     const R xed = xd + l * thr * st + le * (thr + u) * stp;
     const R zed = zd - l * thr * ct - le * (thr + u) * ctp;
@@ -411,11 +432,11 @@ __device__ __forceinline__ void solve_section(
     const R fe = R(0.5 * a.rho * a.s_elev) * (xed * xed + zed * zed) * R(2) * sin(alpha);
     const R fex = -fe * stp, fez = fe * ctp;
     const R fx = R(fwx) + fex, fz = R(fwz) + fez;
-    const R ax_ = fx / R(a.mass);
-    const R az_ = fz / R(a.mass) - R(a.grav);
+    const R ax_ = fx * R(a.inv_mass);
+    const R az_ = fz * R(a.inv_mass) - R(a.grav);
     const R mom = (sh.xw[0] - x) * R(fwz) - (sh.xw[1] - z) * R(fwx) +
                   (xe - x) * fez - (ze - z) * fex + R(mw);
-    const R ath = mom / R(a.inertia);
+    const R ath = mom * R(a.inv_inertia);
     sh.gn[0] = x + dtr * xd;
     sh.gn[1] = z + dtr * zd;
     sh.gn[2] = th + dtr * thr;
@@ -435,34 +456,98 @@ __device__ __forceinline__ void solve_section(
   }
 }
 
-// All threads: edge and bound terms (FIFO order), then advect and decay.
+// Pass-B sources [q0, q1) of the list LEV, TEV, bound 0 .. N_b - 1 (FIFO
+// order) at (x, z), added to (ex, ez). Bound positions and strengths are read
+// from LDS 8 at a time (entries past the range repeat the last position with
+// zero strength, which adds exactly nothing).
+template <typename R>
+__device__ inline void pass_b_sum(const KArgs &a, const Shared<R> &sh, R x, R z, R rc4,
+                                  int q0, int q1, R &ex, R &ez) {
+  if (q0 <= 0 && q1 > 0) reg_term(x - sh.lev[0], z - sh.lev[1], sh.shed_g[0], rc4, ex, ez);
+  if (q0 <= 1 && q1 > 1) reg_term(x - sh.tev[0], z - sh.tev[1], sh.shed_g[1], rc4, ex, ez);
+  const int jlo = q0 > 2 ? q0 - 2 : 0, jhi = q1 - 2;
+  for (int j0 = jlo; j0 < jhi; j0 += 8) {
+    R bx[8], bz[8], bg[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = j0 + q < jhi ? j0 + q : jhi - 1;
+      bx[q] = sh.bpos[j][0];
+      bz[q] = sh.bpos[j][1];
+      bg[q] = j0 + q < jhi ? sh.bgam[j] : R(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sing_term(x - bx[q], z - bz[q], bg[q], ex, ez);
+  }
+}
+
+// Wake vortex t of the step: total velocity (pass A + edge and bound terms),
+// optional output, Euler advection and decay.
+template <typename R>
+__device__ inline void pass_b_finish(const KArgs &a, typename SrcOf<R>::type *src,
+                                     const Vec2<R> *vel, int k, bool last, int head, int t,
+                                     double ex, double ez, R one_decay) {
+  const int p = head + t;
+  auto s = src[p];
+  const Vec2<R> v0 = vel[p];
+  const double vx = double(v0.x) + ex, vz = double(v0.z) + ez;
+  if (last && a.vel_last) {
+    double *o = a.vel_last + 2 * (a.wake_off[k] + t);
+    o[0] = vx;
+    o[1] = vz;
+  }
+  const R dtr = R(a.dt);
+  s.x = s.x + dtr * R(vx);
+  s.z = s.z + dtr * R(vz);
+  s.g = s.g * one_decay;
+  src[p] = s;
+}
+
+// All waves: the m wake vortices in groups of 64 (group i to wave i mod NW),
+// each lane one vortex against every pass-B source. A last group of r < 32
+// vortices goes to one wave whose lanes split the sources into 64 / r parts,
+// added in FP64 in part order through `scratch` (64 double2 per wave).
 template <typename R>
 __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
                                        typename SrcOf<R>::type *src,
                                        const Vec2<R> *vel, int k, bool last,
-                                       int head, int m, int tid, int nthr) {
-  using Src = typename SrcOf<R>::type;
+                                       int head, int m, int tid, int nthr,
+                                       double2 *scratch) {
   const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
-  const R one_decay = R(1.0 - a.decay * a.dt), dtr = R(a.dt);
-  for (int t = tid; t < m; t += nthr) {
-    const int p = head + t;
-    Src s = src[p];
-    const Vec2<R> v0 = vel[p];
-    R ex = R(0), ez = R(0);
-    reg_term(s.x - sh.lev[0], s.z - sh.lev[1], sh.shed_g[0], rc4, ex, ez);
-    reg_term(s.x - sh.tev[0], s.z - sh.tev[1], sh.shed_g[1], rc4, ex, ez);
-    for (int j = 0; j < a.nb; ++j)
-      sing_term(s.x - sh.bpos[j][0], s.z - sh.bpos[j][1], sh.bgam[j], ex, ez);
-    const double vx = double(v0.x) + double(ex), vz = double(v0.z) + double(ez);
-    if (last && a.vel_last) {
-      double *o = a.vel_last + 2 * (a.wake_off[k] + t);
-      o[0] = vx;
-      o[1] = vz;
+  const R one_decay = R(1.0 - a.decay * a.dt);
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nw = nthr >> 6, ns = a.nb + 2;
+  const int r = m & 63, tail = r < 32 ? r : 0;
+  const int n_groups = (m >> 6) + (r >= 32 ? 1 : 0);
+  for (int gi = wave; gi < n_groups; gi += nw) {
+    const int t = gi * 64 + lane;
+    if (t < m) {
+      const auto s = src[head + t];
+      R ex = R(0), ez = R(0);
+      pass_b_sum(a, sh, s.x, s.z, rc4, 0, ns, ex, ez);
+      pass_b_finish(a, src, vel, k, last, head, t, double(ex), double(ez), one_decay);
     }
-    s.x = s.x + dtr * R(vx);
-    s.z = s.z + dtr * R(vz);
-    s.g = s.g * one_decay;
-    src[p] = s;
+  }
+  if (tail > 0 && wave == n_groups % nw) {
+    const int t0 = n_groups * 64, g = 64 / tail, tt = lane % tail, part = lane / tail;
+    R ex = R(0), ez = R(0);
+    if (part < g) {
+      const auto s = src[head + t0 + tt];
+      pass_b_sum(a, sh, s.x, s.z, rc4, (ns * part) / g, (ns * (part + 1)) / g, ex, ez);
+    }
+    double2 *sc = scratch + wave * 64;
+    sc[lane] = make_double2(double(ex), double(ez));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < tail) {
+      double sx = 0.0, sz = 0.0;
+      for (int q = 0; q < g; ++q) {
+        const double2 d = sc[q * tail + lane];
+        sx += d.x;
+        sz += d.y;
+      }
+      pass_b_finish(a, src, vel, k, last, head, t0 + lane, sx, sz, one_decay);
+    }
   }
 }
 
@@ -598,6 +683,27 @@ __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
   red[wave * 64 + lane] = Vec2<R>{sx[0] + cx[0], sz[0] + cz[0]};
 }
 
+// Issue priority of this wave for step n. Several rollouts share a CU, and
+// the sequencer issues from the oldest wave first, so with equal priorities
+// the first-dispatched workgroup runs at almost solo speed and the last one
+// finishes long after, alone on an idle CU. Rotating the priority by step
+// over four slots makes co-resident workgroups progress at the same rate.
+// The slot is the SIMD of the workgroup's first wave (hardware register
+// HW_ID), which the dispatcher gives to co-resident workgroups in turn.
+__device__ inline void rotate_priority(int slot, int n) {
+  switch ((slot + n) & 3) {
+    case 0: __builtin_amdgcn_s_setprio(3); break;
+    case 1: __builtin_amdgcn_s_setprio(2); break;
+    case 2: __builtin_amdgcn_s_setprio(1); break;
+    default: __builtin_amdgcn_s_setprio(0); break;
+  }
+}
+
+__device__ inline int simd_id() {
+  // HW_ID bits [5:4]: SIMD of this wave
+  return static_cast<int>((__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11)) >> 4) & 3u);
+}
+
 // LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
@@ -616,6 +722,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n_surf = 2 * a.nb + 3;
   for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
+  if (tid == 0) sh.slot = simd_id();
   int fallback = blockIdx.x;
   for (;;) {
     const int k = claim(qu, sh, tid, fallback);
@@ -629,6 +736,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         if (tid == 0) prologue(a, sh, src);
         __syncthreads();
       }
+      rotate_priority(sh.slot, n);
       const int head = sh.head, n_w = sh.n_w;
       const int NT = n_surf + n_w;
 
@@ -673,7 +781,8 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 
       if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
       __syncthreads();
-      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr);
+      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr,
+             reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
       if (tid == 0) epilogue(a, sh, src, k, n, n_w);
       __syncthreads();
@@ -772,7 +881,8 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       __syncthreads();
       if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
       __syncthreads();
-      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr);
+      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr,
+             reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
       if (tid == 0) epilogue(a, sh, src, k, n, n_w);
       __syncthreads();
@@ -1072,6 +1182,10 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.grav = p->grav;
   a.mass = p->mass;
   a.inertia = p->inertia;
+  a.inv_dt = 1.0 / in->dt;
+  a.inv_lb = p->n_bound / p->chord;
+  a.inv_mass = 1.0 / p->mass;
+  a.inv_inertia = 1.0 / p->inertia;
   a.l_body = p->l_body;
   a.l_wing = p->l_wing;
   a.l_elev = p->l_elev;

@@ -129,6 +129,8 @@ inline long long __double_as_longlong(double d) { long long r; memcpy(&r, &d, 8)
 inline double __longlong_as_double(long long v) { double r; memcpy(&r, &v, 8); return r; }
 #define __builtin_amdgcn_wave_barrier() emu_blk->wbar[threadIdx.x >> 6]->arrive_and_wait()
 #define __builtin_amdgcn_fence(a, b) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_s_setprio(p) ((void)0)
+#define __builtin_amdgcn_s_getreg(r) ((unsigned)(threadIdx.x >> 6) << 4)
 #define __builtin_amdgcn_rsqf(x) (1.0f / std::sqrt((float)(x)))
 #define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
 inline unsigned long long wall_clock64() { return 0; }
