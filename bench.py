@@ -46,6 +46,9 @@ def parse():
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", choices=["on", "off"], default=None,
+                    help="capture one MPPI step (rollout batch + weights) in a HIP graph after "
+                         "the warm-up and time its replays (default: on for the uneven batch)")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests of the serving trace to replay (0: skip)")
     ap.add_argument("--slice", type=int, default=None,
@@ -125,7 +128,8 @@ def measured_traffic(workload):
 
 def cpu_baseline(name, wl):
     """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload, all host cores (OpenMP over rollouts)."""
+    workload, all host cores (OpenMP over rollouts). Returns the baseline
+    record, the sampled workload and the oracle's outputs on it."""
     from oracle import oracle as O
     from paper_2509_16079_amd import workloads as W
     O.build(force=False)
@@ -142,17 +146,17 @@ def cpu_baseline(name, wl):
         idx = order[np.linspace(0, wl.K - 1, 64).astype(np.int64)]
         what = "64 rollouts stratified by initial wake size, full horizon H=100"
     else:
-        idx = np.arange(16)
+        idx = np.linspace(0, wl.K - 1, 64).astype(np.int64)
         H = 1
-        what = "16 rollouts, first step only (1 of 150), per-pair rate"
+        what = "64 rollouts (evenly spaced), first step only (1 of 150), per-pair rate"
     sub = wl.subset(idx)
     if H != wl.H:
         from dataclasses import replace
         sub = replace(sub, H=H, u_mean=sub.u_mean[:H], u_eps=sub.u_eps[:, :H])
     t0 = time.perf_counter()
-    O.rollout_batch(sub.params, sub.K, sub.H, sub.dt, sub.g0, sub.gb0, sub.field_off,
-                    sub.field_of, sub.wx, sub.wz, sub.wg, sub.pairs, sub.u, sub.x_goal,
-                    sub.q_diag, n_threads=threads)
+    o = O.rollout_batch(sub.params, sub.K, sub.H, sub.dt, sub.g0, sub.gb0, sub.field_off,
+                        sub.field_of, sub.wx, sub.wz, sub.wg, sub.pairs, sub.u, sub.x_goal,
+                        sub.q_diag, final_wake=True, n_threads=threads)
     dt = time.perf_counter() - t0
     pairs = sum(sum(W.pair_count(int(n), H, sub.params["n_bound"],
                                  n_wake_max=sub.params["n_wake_max"])) for n in sub.n0)
@@ -160,7 +164,60 @@ def cpu_baseline(name, wl):
            "kind": "oracle", "seconds": dt, "sample": what + "; OpenMP over rollouts"}
     if H == wl.H:
         out["rollouts_per_s"] = len(idx) / dt
-    return out
+    o["mppi"] = O.mppi(o["cost"], sub.lam, sub.u_mean, sub.u_eps)
+    if name in ("realtime", "plain", "uneven"):
+        # the oracle against itself with every velocity sum in reverse order:
+        # the amplification of rounding differences by the flow over this
+        # horizon, i.e. the floor no other summation order can beat
+        r = O.rollout_batch(sub.params, sub.K, sub.H, sub.dt, sub.g0, sub.gb0, sub.field_off,
+                            sub.field_of, sub.wx, sub.wz, sub.wg, sub.pairs, sub.u, sub.x_goal,
+                            sub.q_diag, reverse=True, n_threads=threads)
+        o["self_divergence"] = {
+            "final_state_rel_l2": _rel_l2(r["g_final"], o["g_final"]),
+            "mppi_argmin_equal": O.mppi(r["cost"], sub.lam, sub.u_mean, sub.u_eps)["argmin"]
+                                 == o["mppi"]["argmin"]}
+    return out, sub, o
+
+
+def _rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    d = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (d if d > 0 else 1.0))
+
+
+def error_vs_oracle(V, ctx, sub, o, prec, horizon_note):
+    """The GPU path on the oracle's sample (same inputs, same horizon), in an
+    extra launch outside the timed region, against the oracle's outputs."""
+    import torch
+    db = V.DeviceBatch(sub)
+    out = V.DeviceOutputs(db, final_wake=True)
+    ctx.rollout(sub.params, db, out, prec)
+    w, _, am, _ = ctx.mppi(out.cost, sub.lam, db.u_mean, db.u_eps)
+    torch.cuda.synchronize()
+    g = out.to_numpy()
+    seg_g, seg_o, circ = [], [], []
+    for k in range(sub.K):
+        n = int(g["n_final"][k])
+        a0, b0 = int(g["out_off"][k]), int(o["out_off"][k])
+        gx = np.concatenate([g["wx"][a0:a0 + n], g["wz"][a0:a0 + n]])
+        ox = np.concatenate([o["wx"][b0:b0 + n], o["wz"][b0:b0 + n]])
+        seg_g.append(gx)
+        seg_o.append(ox)
+        og = o["wg"][b0:b0 + n]
+        circ.append(abs(g["wg"][a0:a0 + n].sum() - og.sum()) / max(np.abs(og).sum(), 1e-300))
+    finite = np.isfinite(o["cost"])
+    return {
+        "horizon": horizon_note,
+        "final_state_rel_l2": _rel_l2(g["g_final"], o["g_final"]),
+        "cost_max_rel": float(np.max(np.abs(g["cost"][finite] - o["cost"][finite])
+                                     / np.abs(o["cost"][finite]))) if finite.any() else None,
+        "final_wake_positions_rel_l2": _rel_l2(np.concatenate(seg_g), np.concatenate(seg_o)),
+        "circulation_drift_max": float(max(circ)) if circ else 0.0,
+        "wake_counts_equal": bool(np.array_equal(g["n_final"], o["n_final"])),
+        "mppi_weights_max_abs": float(np.max(np.abs(w.cpu().numpy() - o["mppi"]["w"]))),
+        "mppi_argmin_equal": int(am.item()) == o["mppi"]["argmin"],
+    }
 
 
 def serving(n_requests):
@@ -266,12 +323,32 @@ def main():
         dst = src.clone()
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(warmup):
+    use_graph = (args.graph == "on") or (args.graph is None and args.workload == "uneven")
+    if use_graph and 0 < slice_k < wl.K:
+        sys.exit("--graph needs the whole batch in one launch (use --slice 0)")
+    for _ in range(max(warmup, 1 if use_graph else 0)):
         step()
     torch.cuda.synchronize()
+    graph = None
+    if use_graph:
+        # the eager warm-up sized every buffer; the capture allocates nothing
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            cs = torch.cuda.current_stream()
+            ctx.rollout(wl.params, db, out, prec, cs)
+            ctx.mppi(out.cost, wl.lam, db.u_mean, db.u_eps, cs)
+        graph.replay()
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        step(timed=True)
+        if graph is None:
+            step(timed=True)
+        else:
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record(stream)
+            graph.replay()
+            ev[1].record(stream)
+            kernel_ms.append(ev)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert int(out.pair_count.sum().item()) == pairs_per_step
@@ -298,6 +375,10 @@ def main():
         "pairs_per_step": pairs_per_step,
         "rollout_kernel_ms": kern_avg,
         "launch_slices": 1 if slice_k <= 0 or slice_k >= wl.K else -(-wl.K // slice_k),
+        "hip_graph": graph is not None,
+        "kernel_timing": ("HIP events around each replay of the captured graph (rollout batch "
+                          "+ MPPI weights)") if graph is not None else
+                         "HIP events around each rollout launch on its stream",
         "nonfinite_rollouts": int(np.sum(status != 0)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
@@ -310,7 +391,16 @@ def main():
     if n_serve > 0:
         line["serving"] = serving(n_serve)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, wl)
+        base, sub, o = cpu_baseline(args.workload, wl)
+        line["cpu_baseline"] = base
+        ctx = V.Context(0)
+        note = "%d steps on the oracle's sample (%s)" % (sub.H, base["sample"])
+        line["error_vs_oracle"] = {prec_name: error_vs_oracle(V, ctx, sub, o, prec, note)}
+        if prec == V.FP32C:
+            line["error_vs_oracle"]["fp64"] = error_vs_oracle(V, ctx, sub, o, V.FP64, note)
+        if "self_divergence" in o:
+            line["error_vs_oracle"]["oracle_reverse_order"] = o["self_divergence"]
+        ctx.close()
     print(json.dumps(line), flush=True)
 
 
