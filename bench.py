@@ -161,7 +161,20 @@ def cpu_baseline(name, wl):
     pairs = sum(sum(W.pair_count(int(n), H, sub.params["n_bound"],
                                  n_wake_max=sub.params["n_wake_max"])) for n in sub.n0)
     out = {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads,
-           "kind": "oracle", "seconds": dt, "sample": what + "; OpenMP over rollouts"}
+           "kind": "oracle", "seconds": dt, "sample": what + "; OpenMP over rollouts",
+           "cpu_model": cpu_model()}
+    if name in ("plain", "realtime"):
+        # one thread, on the first 32 rollouts of the sample
+        one = sub.subset(np.arange(min(32, sub.K)))
+        t1 = time.perf_counter()
+        O.rollout_batch(one.params, one.K, one.H, one.dt, one.g0, one.gb0, one.field_off,
+                        one.field_of, one.wx, one.wz, one.wg, one.pairs, one.u, one.x_goal,
+                        one.q_diag, n_threads=1)
+        d1 = time.perf_counter() - t1
+        p1 = sum(sum(W.pair_count(int(n), H, one.params["n_bound"],
+                                  n_wake_max=one.params["n_wake_max"])) for n in one.n0)
+        out["single_thread"] = {"value": p1 / d1, "rollouts_per_s": one.K / d1,
+                                "seconds": d1, "sample": "%d rollouts, full horizon" % one.K}
     if H == wl.H:
         out["rollouts_per_s"] = len(idx) / dt
     o["mppi"] = O.mppi(o["cost"], sub.lam, sub.u_mean, sub.u_eps)
@@ -177,6 +190,30 @@ def cpu_baseline(name, wl):
             "mppi_argmin_equal": O.mppi(r["cost"], sub.lam, sub.u_mean, sub.u_eps)["argmin"]
                                  == o["mppi"]["argmin"]}
     return out, sub, o
+
+
+def gpu_clock():
+    """Current shader and memory clocks as rocm-smi reports them (read after
+    the timed region; None if the tool is unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=20)
+        d = json.loads(r.stdout)
+        card = d[sorted(d)[0]]
+        return {k: v for k, v in card.items() if "sclk" in k.lower() or "mclk" in k.lower()}
+    except Exception:
+        return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _rel_l2(a, b):
@@ -352,7 +389,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert int(out.pair_count.sum().item()) == pairs_per_step
-    kern_avg = float(sum(a.elapsed_time(b) for a, b in kernel_ms) / steps)
+    kern_each = [a.elapsed_time(b) for a, b in kernel_ms]
+    kern_avg = float(sum(kern_each) / steps)
     ms = 1e3 * wall / steps
     status = out.status.cpu().numpy()
     achieved = flop_per_launch / (kern_avg * 1e-3) / 1e12
@@ -374,6 +412,8 @@ def main():
         "rollouts_per_s": wl.K / (ms * 1e-3),
         "pairs_per_step": pairs_per_step,
         "rollout_kernel_ms": kern_avg,
+        "rollout_kernel_ms_median": float(np.median(kern_each)) if kern_each else None,
+        "gpu_clock_after_timed_region": gpu_clock(),
         "launch_slices": 1 if slice_k <= 0 or slice_k >= wl.K else -(-wl.K // slice_k),
         "hip_graph": graph is not None,
         "kernel_timing": ("HIP events around each replay of the captured graph (rollout batch "

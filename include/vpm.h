@@ -187,6 +187,18 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
                               const vpm_batch_in *in, vpm_batch_out *out,
                               void *stream);
 
+/* Prepare the context for later vpm_rollout_batch calls with these or smaller
+ * sizes (K rollouts, H steps, initial wakes of at most max_wake0 vortices in
+ * n_fields fields, the kernel variant set by vpm_set_path): builds the plate
+ * inverse for params' geometry and grows the streaming workspace and the
+ * uneven-batch plan buffer as those calls would. Such calls then allocate
+ * nothing, so they may be the first calls captured into a HIP graph. Not a
+ * step of the method: it serves callers that must not allocate in their hot
+ * loop. Synchronises the device when a buffer grows. Errors: VPM_EINVAL,
+ * VPM_ENOMEM, VPM_ESINGULAR, VPM_EDEVICE. */
+VPM_API int vpm_reserve(vpm_ctx *ctx, const vpm_params *params, int32_t K,
+                        int32_t H, int32_t max_wake0, int32_t n_fields);
+
 /* Standalone batched FP64 surface solve (Eqs. 10-12): for B wing poses
  * pose[b] = (x_w, z_w, th, xd_w, zd_w, thd) with wake-induced velocities
  * vw_c[b][i] (i = 0..N_b, collocation points from LE to TE) and wake
@@ -231,24 +243,29 @@ typedef struct {
   int32_t K, H;             /* rollouts and steps                            */
   double dt;                /* step [s]                                      */
   double lambda;            /* MPPI temperature (Eq. 25), > 0                */
+  int32_t iterations;       /* MPPI iterations, >= 1: iteration i rolls out
+                               the same initial state with the mean updated by
+                               iteration i - 1 (the planner's replan runs 3) */
   double x_goal[7];         /* cost goal (Eq. 24)                            */
   double q_diag[7];         /* cost weights (Eq. 24)                         */
   const double *u_mean;     /* host [H]: copied at submit                    */
-  const double *u_eps;      /* host [K][H]: copied at submit                 */
+  const double *u_eps;      /* host [iterations][K][H]: copied at submit     */
 } plan_req;
 
 typedef struct {
   int32_t status;           /* VPM_OK, or the error the request failed with  */
   int32_t argmin;           /* MPPI argmin (-1 if no finite cost)            */
   double jmin;
-  double *u_new;            /* host [H] caller buffer for the update, or NULL */
-  double *w;                /* host [K] caller buffer for the weights, or NULL */
-  double *cost;             /* host [K] caller buffer for the costs, or NULL  */
+  double *u_new;            /* host [H] caller buffer for the update after the
+                               last iteration, or NULL                       */
+  double *w;                /* host [K] weights of the last iteration, or NULL */
+  double *cost;             /* host [K] costs of the last iteration, or NULL  */
   double *g_final;          /* host [K][7] caller buffer, or NULL            */
   double t_arrive_us;       /* submit time (us since planner_create)        */
   double t_admit_us;        /* admission time                               */
   double t_done_us;         /* completion time (results in host memory)     */
-  int64_t pairs;            /* pair-interactions of the request             */
+  int64_t pairs;            /* pair-interactions of the request (all
+                               iterations)                                   */
 } plan_result;
 
 /* Create / destroy a planner (it owns one context and stream per slot).
@@ -277,10 +294,10 @@ VPM_API int planner_poll(planner *p, uint64_t ticket, plan_result *res,
                          int32_t timeout_us);
 
 /* Device-memory footprint the planner charges a request against its budget
- * (host arithmetic): inputs, outputs and, for wakes beyond the LDS-resident
- * kernel, the streaming workspace. */
+ * (host arithmetic): inputs (perturbations of every iteration), outputs and,
+ * for wakes beyond the LDS-resident kernel, the streaming workspace. */
 VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0,
-                                 int32_t n_bound);
+                                 int32_t n_bound, int32_t iterations);
 
 /* Exact pair-interaction count of one rollout (host arithmetic): per step
  * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b

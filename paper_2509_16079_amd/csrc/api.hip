@@ -167,6 +167,20 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
                              static_cast<hipStream_t>(stream));
 }
 
+VPM_API int vpm_reserve(vpm_ctx *ctx, const vpm_params *params, int32_t K, int32_t H,
+                        int32_t max_wake0, int32_t n_fields) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  int rc = vpm::check_params(params);
+  if (rc != VPM_OK) return rc;
+  if (K < 1 || H < 1 || max_wake0 < 0 || n_fields < 1)
+    return fail(VPM_EINVAL, "K, H, n_fields must be >= 1 and max_wake0 >= 0");
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  const double *kinv = nullptr;
+  rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_BOTH, &kinv, false);
+  if (rc != VPM_OK) return rc;
+  return vpm::reserve_rollout(ctx, params, K, H, max_wake0, n_fields);
+}
+
 VPM_API int vpm_plate_solve(vpm_ctx *ctx, const vpm_params *params, int32_t B,
                             const double *pose, const double *vw_c,
                             const double *sum_gw, int32_t shed_mode,

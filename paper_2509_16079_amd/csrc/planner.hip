@@ -52,7 +52,7 @@ enum class ReqState { kPending, kRunning, kDone };
 struct Request {
   uint64_t ticket = 0, state_id = 0;
   vpm_params params{};
-  int K = 0, H = 0;
+  int K = 0, H = 0, iters = 1;
   double dt = 0, lambda = 1;
   double x_goal[7]{}, q_diag[7]{};
   std::vector<double> u_mean, u_eps;  // host copies
@@ -136,16 +136,18 @@ int grow_pinned(T **ptr, size_t have, size_t need) {
   return VPM_OK;
 }
 
-// Make the slot's buffers hold a K x H request with nb bound vortices
-// (capacities grow by at least 1.5x so a stream of varied requests settles).
-int reserve(Slot &s, size_t K, size_t H, size_t nb) {
-  if (K * H <= s.cap_kh && K <= s.cap_k && H <= s.cap_h && K * nb <= s.cap_kb && s.h_in)
+// Make the slot's buffers hold a request of `iters` K x H perturbation sets
+// with nb bound vortices (capacities grow by at least 1.5x so a stream of
+// varied requests settles).
+int reserve(Slot &s, size_t K, size_t H, size_t nb, size_t iters) {
+  const size_t kh = K * H * iters;
+  if (kh <= s.cap_kh && K <= s.cap_k && H <= s.cap_h && K * nb <= s.cap_kb && s.h_in)
     return VPM_OK;
   if (hipStreamSynchronize(s.stream) != hipSuccess) return VPM_EDEVICE;
   auto up = [](size_t have, size_t need) { return std::max(need, have + have / 2); };
   int rc = VPM_OK;
-  if (K * H > s.cap_kh) {
-    s.cap_kh = up(s.cap_kh, K * H);
+  if (kh > s.cap_kh) {
+    s.cap_kh = up(s.cap_kh, kh);
     rc |= grow(&s.d_u_eps, 0, s.cap_kh);
   }
   if (H > s.cap_h) {
@@ -188,14 +190,15 @@ void finish_request(planner *p, Request *r, int status) {
 // Enqueue request r on slot s (called with the planner lock held).
 int launch(planner *p, Slot &s, Request *r) {
   const State &st = p->states.at(r->state_id);
-  const size_t K = r->K, H = r->H, nb = st.nb;
-  int rc = reserve(s, K, H, nb);
+  const size_t K = r->K, H = r->H, nb = st.nb, it_n = r->iters;
+  int rc = reserve(s, K, H, nb, it_n);
   if (rc != VPM_OK) return fail(rc, "planner slot allocation failed");
-  std::memcpy(s.h_in, r->u_eps.data(), K * H * sizeof(double));
-  std::memcpy(s.h_in + K * H, r->u_mean.data(), H * sizeof(double));
-  VPM_HIP_TRY(hipMemcpyAsync(s.d_u_eps, s.h_in, K * H * sizeof(double),
-                             hipMemcpyHostToDevice, s.stream));
-  VPM_HIP_TRY(hipMemcpyAsync(s.d_u_mean, s.h_in + K * H, H * sizeof(double),
+  const size_t kh = K * H * it_n;
+  std::memcpy(s.h_in, r->u_eps.data(), kh * sizeof(double));
+  std::memcpy(s.h_in + kh, r->u_mean.data(), H * sizeof(double));
+  VPM_HIP_TRY(hipMemcpyAsync(s.d_u_eps, s.h_in, kh * sizeof(double), hipMemcpyHostToDevice,
+                             s.stream));
+  VPM_HIP_TRY(hipMemcpyAsync(s.d_u_mean, s.h_in + kh, H * sizeof(double),
                              hipMemcpyHostToDevice, s.stream));
   hipLaunchKernelGGL(broadcast_state_kernel, dim3((K + 255) / 256), dim3(256), 0, s.stream,
                      r->K, st.nb, st.g7, st.gb, s.d_g0, s.d_gb0, s.d_field_of);
@@ -214,8 +217,6 @@ int launch(planner *p, Slot &s, Request *r) {
   in.wx = st.wx;
   in.wz = st.wz;
   in.wg = st.wg;
-  in.u_mean = s.d_u_mean;
-  in.u_eps = s.d_u_eps;
   std::memcpy(in.x_goal, r->x_goal, sizeof(in.x_goal));
   std::memcpy(in.q_diag, r->q_diag, sizeof(in.q_diag));
   vpm_batch_out out{};
@@ -223,16 +224,25 @@ int launch(planner *p, Slot &s, Request *r) {
   out.cost = s.d_cost;
   out.status = s.d_status;
   out.pair_count = s.d_pairs;
-  rc = vpm_rollout_batch(s.ctx, &r->params, &in, &out, s.stream);
-  if (rc != VPM_OK) return rc;
-  rc = mppi_weights(s.ctx, r->K, r->H, s.d_cost, r->lambda, s.d_u_mean, s.d_u_eps, s.d_w,
-                    s.d_u_new, s.d_argmin, s.d_jmin, s.stream);
-  if (rc != VPM_OK) return rc;
+  // MPPI iterations (Sec. IV-A): each rolls the same initial state out under
+  // its own perturbations around the previous iteration's update; the mean
+  // alternates between the two device buffers
+  double *mean = s.d_u_mean, *next = s.d_u_new;
+  for (size_t i = 0; i < it_n; ++i) {
+    in.u_mean = mean;
+    in.u_eps = s.d_u_eps + i * K * H;
+    rc = vpm_rollout_batch(s.ctx, &r->params, &in, &out, s.stream);
+    if (rc != VPM_OK) return rc;
+    rc = mppi_weights(s.ctx, r->K, r->H, s.d_cost, r->lambda, mean, in.u_eps, s.d_w, next,
+                      s.d_argmin, s.d_jmin, s.stream);
+    if (rc != VPM_OK) return rc;
+    std::swap(mean, next);
+  }
   double *h = s.h_out;
   VPM_HIP_TRY(hipMemcpyAsync(h, s.d_cost, K * 8, hipMemcpyDeviceToHost, s.stream));
   VPM_HIP_TRY(hipMemcpyAsync(h + K, s.d_w, K * 8, hipMemcpyDeviceToHost, s.stream));
   VPM_HIP_TRY(hipMemcpyAsync(h + 2 * K, s.d_g_final, 7 * K * 8, hipMemcpyDeviceToHost, s.stream));
-  VPM_HIP_TRY(hipMemcpyAsync(h + 9 * K, s.d_u_new, H * 8, hipMemcpyDeviceToHost, s.stream));
+  VPM_HIP_TRY(hipMemcpyAsync(h + 9 * K, mean, H * 8, hipMemcpyDeviceToHost, s.stream));
   VPM_HIP_TRY(hipMemcpyAsync(h + 9 * K + H, s.d_jmin, 8, hipMemcpyDeviceToHost, s.stream));
   VPM_HIP_TRY(hipMemcpyAsync(s.h_argmin, s.d_argmin, 4, hipMemcpyDeviceToHost, s.stream));
   VPM_HIP_TRY(hipMemcpyAsync(s.h_pairs, s.d_pairs, K * 8, hipMemcpyDeviceToHost, s.stream));
@@ -252,6 +262,7 @@ void collect(planner *p, Slot &s) {
   r->argmin = *s.h_argmin;
   r->pairs = 0;
   for (size_t k = 0; k < K; ++k) r->pairs += s.h_pairs[k];
+  r->pairs *= r->iters;  // the wake-count schedule, so the work, is the same each iteration
 }
 
 void worker_loop(planner *p) {
@@ -348,9 +359,11 @@ using vpm::fail;
 
 extern "C" {
 
-VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0, int32_t n_bound) {
+VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0, int32_t n_bound,
+                                 int32_t iterations) {
   const size_t k = K > 0 ? K : 0, h = H > 0 ? H : 0, nb = n_bound > 0 ? n_bound : 0;
-  size_t bytes = 8 * (k * h + 2 * h + 7 * k + k * nb + 7 * k + 3 * k + 1) + 4 * (2 * k + 1);
+  const size_t it = iterations > 0 ? iterations : 1;
+  size_t bytes = 8 * (it * k * h + 2 * h + 7 * k + k * nb + 7 * k + 3 * k + 1) + 4 * (2 * k + 1);
   // wakes beyond the LDS-resident kernel take a streaming workspace of
   // 24 B per vortex of capacity for each of the GPU's 256 CUs
   const size_t cap = (size_t)(n0 > 0 ? n0 : 0) + 2 * h;
@@ -456,8 +469,8 @@ VPM_API int planner_state_drop(planner *p, uint64_t state_id) {
 VPM_API int planner_submit(planner *p, const plan_req *req, uint64_t *ticket) {
   if (!p || !req || !ticket) return fail(VPM_EINVAL, "NULL argument");
   if (req->K < 1 || req->H < 1 || !(req->dt > 0) || !(req->lambda > 0) || !req->u_mean ||
-      !req->u_eps)
-    return fail(VPM_EINVAL, "bad request sizes or pointers");
+      !req->u_eps || req->iterations < 1 || req->iterations > 64)
+    return fail(VPM_EINVAL, "bad request sizes, iterations (1..64) or pointers");
   auto r = std::make_unique<vpm::Request>();
   {
     std::lock_guard<std::mutex> lock(p->mu);
@@ -465,7 +478,8 @@ VPM_API int planner_submit(planner *p, const plan_req *req, uint64_t *ticket) {
     if (it == p->states.end()) return fail(VPM_ENOTFOUND, "unknown state");
     if (req->params.n_bound != it->second.nb)
       return fail(VPM_EINVAL, "params.n_bound differs from the state's");
-    r->footprint = planner_footprint(req->K, req->H, it->second.n, it->second.nb);
+    r->footprint =
+        planner_footprint(req->K, req->H, it->second.n, it->second.nb, req->iterations);
     if (r->footprint > p->budget) return fail(VPM_EBUDGET, "request exceeds the HBM budget");
   }
   r->state_id = req->state_id;
@@ -474,10 +488,11 @@ VPM_API int planner_submit(planner *p, const plan_req *req, uint64_t *ticket) {
   r->H = req->H;
   r->dt = req->dt;
   r->lambda = req->lambda;
+  r->iters = req->iterations;
   std::memcpy(r->x_goal, req->x_goal, sizeof(r->x_goal));
   std::memcpy(r->q_diag, req->q_diag, sizeof(r->q_diag));
   r->u_mean.assign(req->u_mean, req->u_mean + req->H);
-  r->u_eps.assign(req->u_eps, req->u_eps + (size_t)req->K * req->H);
+  r->u_eps.assign(req->u_eps, req->u_eps + (size_t)req->iterations * req->K * req->H);
   std::lock_guard<std::mutex> lock(p->mu);
   auto it = p->states.find(req->state_id);
   if (it == p->states.end()) return fail(VPM_ENOTFOUND, "unknown state");

@@ -1155,6 +1155,36 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 
 }  // namespace
 
+// Grow the context buffers that a batch of these sizes would need (the same
+// class decisions as run_batch), outside any stream capture.
+template <typename R, int TMAX_L>
+int reserve_batch(vpm_ctx *ctx, int nb, int K, int cap, int n_fields) {
+  constexpr int kNwLarge = sizeof(R) == 4 ? 16 : 8;
+  const int cap_large = lds_capacity<R>(nb, nb + 2, kNwLarge, TMAX_L, ctx->max_lds);
+  const int path = ctx->path;
+  std::lock_guard<std::mutex> lock(ctx->ws_mu);
+  if (path == VPM_PATH_STREAM || (path == VPM_PATH_AUTO && cap > cap_large)) {
+    const int grid = K < ctx->n_cu ? K : ctx->n_cu;
+    const size_t slot = (size_t)cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
+    const int rc = ensure_buffer(&ctx->ws, &ctx->ws_bytes, slot * grid, "streaming workspace",
+                                 false);
+    if (rc != VPM_OK) return rc;
+  }
+  if (path == VPM_PATH_AUTO && n_fields > 1) {
+    const size_t plan_bytes = (size_t)K * sizeof(int32_t) + 64;
+    const int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan", false);
+    if (rc != VPM_OK) return rc;
+  }
+  return VPM_OK;
+}
+
+int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wake0,
+                    int n_fields) {
+  const int cap = max_wake0 + 2 * H;
+  if (p->precision == VPM_FP64) return reserve_batch<double, 2>(ctx, p->n_bound, K, cap, n_fields);
+  return reserve_batch<float, 2>(ctx, p->n_bound, K, cap, n_fields);
+}
+
 int lds_resident_capacity(int nb) {
   return lds_capacity<float>(nb, nb + 2, 16, 2, 163840);
 }

@@ -91,6 +91,11 @@ bool stream_capturing(hipStream_t stream);
 // gfx950 workgroup (160 KB of LDS); larger wakes take the streaming kernel.
 int lds_resident_capacity(int nb);
 
+// Grow the context's workspace and plan buffers for later batches of these
+// sizes (vpm_reserve).
+int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wake0,
+                    int n_fields);
+
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
                    vpm_batch_out *out, const double *kinv_t,
                    hipStream_t stream);

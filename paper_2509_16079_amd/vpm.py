@@ -67,6 +67,7 @@ def lib():
         L.vpm_plate_solve.argtypes = [_P, C.POINTER(Params), _I, _P, _P, _P, _I, _P, _P]
         L.mppi_weights.argtypes = [_P, _I, _I, _P, _D, _P, _P, _P, _P, _P, _P, _P]
         L.vpm_set_path.argtypes = [_P, C.c_int]
+        L.vpm_reserve.argtypes = [_P, C.POINTER(Params), _I, _I, _I, _I]
         L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
         L.vpm_pair_count.restype = C.c_int64
         _lib = L
@@ -235,6 +236,13 @@ class Context:
         except Exception:
             pass
 
+    def reserve(self, params: dict, K, H, max_wake0, n_fields=1, precision=FP32C):
+        """``vpm_reserve``: size the context so that later batches no larger
+        than this allocate nothing (and may be captured into a graph first)."""
+        p = make_params(params, precision)
+        check(lib().vpm_reserve(self.h, C.byref(p), int(K), int(H), int(max_wake0),
+                                int(n_fields)), "vpm_reserve")
+
     def rollout(self, params: dict, db: DeviceBatch, out: DeviceOutputs, precision=FP32C,
                 stream=None, k0=0, k1=None):
         """Enqueue ``vpm_rollout_batch`` on ``stream`` (default: torch's current)
@@ -292,8 +300,8 @@ class PlannerOpts(C.Structure):
 
 class PlanReq(C.Structure):
     _fields_ = [("state_id", C.c_uint64), ("params", Params), ("K", _I), ("H", _I), ("dt", _D),
-                ("lam", _D), ("x_goal", _D * 7), ("q_diag", _D * 7), ("u_mean", _P),
-                ("u_eps", _P)]
+                ("lam", _D), ("iterations", _I), ("x_goal", _D * 7), ("q_diag", _D * 7),
+                ("u_mean", _P), ("u_eps", _P)]
 
 
 class PlanResult(C.Structure):
@@ -312,14 +320,15 @@ def _planner_lib():
         L.planner_state_drop.argtypes = [_P, C.c_uint64]
         L.planner_submit.argtypes = [_P, C.POINTER(PlanReq), C.POINTER(C.c_uint64)]
         L.planner_poll.argtypes = [_P, C.c_uint64, C.POINTER(PlanResult), _I]
-        L.planner_footprint.argtypes = [_I, _I, _I, _I]
+        L.planner_footprint.argtypes = [_I, _I, _I, _I, _I]
         L.planner_footprint.restype = C.c_size_t
         L._planner_ready = True
     return L
 
 
-def planner_footprint(K, H, n0, n_bound):
-    return int(_planner_lib().planner_footprint(int(K), int(H), int(n0), int(n_bound)))
+def planner_footprint(K, H, n0, n_bound, iterations=1):
+    return int(_planner_lib().planner_footprint(int(K), int(H), int(n0), int(n_bound),
+                                                int(iterations)))
 
 
 class Planner:
@@ -358,13 +367,17 @@ class Planner:
 
     def submit(self, sid, params: dict, u_mean, u_eps, dt, lam=1.0, x_goal=None, q_diag=None,
                precision=FP32C):
+        """Queue one request; ``u_eps`` is [K, H] (one MPPI iteration) or
+        [iterations, K, H]."""
         u_mean = np.ascontiguousarray(u_mean, dtype=np.float64)
         u_eps = np.ascontiguousarray(u_eps, dtype=np.float64)
-        K, H = u_eps.shape
+        if u_eps.ndim == 2:
+            u_eps = u_eps[None]
+        iters, K, H = u_eps.shape
         r = PlanReq()
         r.state_id = int(sid)
         r.params = make_params(params, precision)
-        r.K, r.H, r.dt, r.lam = K, H, float(dt), float(lam)
+        r.K, r.H, r.dt, r.lam, r.iterations = K, H, float(dt), float(lam), iters
         from . import workloads as W
         xg = W.X_GOAL if x_goal is None else x_goal
         qd = W.Q_POS_PITCH if q_diag is None else q_diag

@@ -73,3 +73,28 @@ def test_capture_refuses_to_allocate():
         assert torch.all(out.status == 0)
     finally:
         ctx.close()
+
+
+def test_reserve_allows_capturing_a_first_call():
+    """After vpm_reserve, a batch that was never run eagerly can be captured
+    (nothing to allocate) and its replays equal an eager run."""
+    wl = W.uneven_batch(K=24, H=3, n_min=10, n_max=7000)
+    ctx = V.Context(0)
+    try:
+        db = V.DeviceBatch(wl)
+        out = V.DeviceOutputs(db)
+        ctx.reserve(wl.params, wl.K, wl.H, db.max_wake0, db.n_fields, V.FP32C)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.rollout(wl.params, db, out, V.FP32C)
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.g_final.clone()
+        ref_out = V.DeviceOutputs(db)
+        ctx.rollout(wl.params, db, ref_out, V.FP32C)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref_out.g_final)
+        del g
+    finally:
+        ctx.close()

@@ -129,3 +129,35 @@ def test_errors_and_oracle_check():
         p.drop_state(sid)
     finally:
         p.close()
+
+
+def test_multi_iteration_request_equals_chained_direct_calls():
+    """A request of three MPPI iterations (the paper's planner runs three per
+    replan) equals three direct rollout batches from the same initial state,
+    each around the previous iteration's update, bitwise."""
+    params = W.make_params(32)
+    state = _states(1)[0]
+    rng = np.random.default_rng(8)
+    K, H, iters = 96, 12, 3
+    eps = W.f32(rng.normal(0, 0.15, (iters, K, H)))
+    mu = W.f32(rng.normal(0, 0.05, H))
+    g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
+    planner = V.Planner(max_slots=2)
+    try:
+        sid = planner.put_state(*state, g0, np.zeros(32))
+        res = planner.poll(planner.submit(sid, params, mu, eps, float(W.f32(0.005))), -1)
+    finally:
+        planner.close()
+    assert res["status"] == 0
+    ctx = V.Context(0)
+    try:
+        mean = mu.astype(np.float64)
+        for i in range(iters):
+            d = _direct(ctx, params, state, dict(K=K, H=H, eps=eps[i], mu=mean))
+            mean = d["u_new"]
+    finally:
+        ctx.close()
+    for key in ("cost", "w", "u_new", "g_final"):
+        assert np.array_equal(res[key], d[key]), key
+    assert res["argmin"] == d["argmin"]
+    assert res["pairs"] == iters * K * V.pair_count(len(state[0]), H, 32, 0)

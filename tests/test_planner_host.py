@@ -21,3 +21,9 @@ def test_create_rejects_bad_options():
         assert L.planner_create(C.byref(h), C.byref(o)) == V.EINVAL
     assert L.planner_submit(None, None, None) == V.EINVAL
     assert L.planner_poll(None, 1, None, 0) == V.EINVAL
+
+
+def test_footprint_counts_the_perturbations_of_every_iteration():
+    one = V.planner_footprint(256, 50, 500, 32)
+    three = V.planner_footprint(256, 50, 500, 32, iterations=3)
+    assert three - one == 2 * 8 * 256 * 50
