@@ -46,6 +46,9 @@ def parse():
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="kernel-shape table written by paper_2509_16079_amd.autotune "
+                         "(default: the packaged table if present; 'none': library defaults)")
     ap.add_argument("--graph", choices=["on", "off"], default=None,
                     help="capture one MPPI step (rollout batch + weights) in a HIP graph after "
                          "the warm-up and time its replays (default: on for the uneven batch)")
@@ -192,6 +195,20 @@ def cpu_baseline(name, wl):
     return out, sub, o
 
 
+def apply_tuning(ctx, path):
+    """Load the autotuner's table into the context; returns what runs."""
+    from paper_2509_16079_amd import autotune as A
+    from paper_2509_16079_amd import vpm as V
+    if path is None:
+        path = A.DEFAULT_TABLE if os.path.exists(A.DEFAULT_TABLE) else "none"
+    if path != "none":
+        A.apply(ctx, A.load(path))
+    shapes = {V.CLASS_NAMES[c]: "%d targets/thread, %d-source tiles" % ctx.get_tuning(c)
+              for c in (V.CLASS_SMALL, V.CLASS_LARGE, V.CLASS_STREAM)}
+    return {"table": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__)))
+            if path != "none" else None, "fp32_shapes": shapes}
+
+
 def gpu_clock():
     """Current shader and memory clocks as rocm-smi reports them (read after
     the timed region; None if the tool is unavailable)."""
@@ -322,6 +339,7 @@ def main():
     prec_name = args.precision or prec_name
     prec = V.FP32C if prec_name == "fp32c" else V.FP64
     ctx = V.Context(0)
+    tuning = apply_tuning(ctx, args.tuning)
     db = V.DeviceBatch(wl)
     out = V.DeviceOutputs(db, pair_count=True)
     stream = torch.cuda.current_stream()
@@ -416,6 +434,7 @@ def main():
         "gpu_clock_after_timed_region": gpu_clock(),
         "launch_slices": 1 if slice_k <= 0 or slice_k >= wl.K else -(-wl.K // slice_k),
         "hip_graph": graph is not None,
+        "tuning": tuning,
         "kernel_timing": ("HIP events around each replay of the captured graph (rollout batch "
                           "+ MPPI weights)") if graph is not None else
                          "HIP events around each rollout launch on its stream",

@@ -156,6 +156,28 @@ VPM_API void vpm_destroy(vpm_ctx *ctx);
  * and serialised across streams. Returns VPM_EINVAL for an unknown value. */
 VPM_API int vpm_set_path(vpm_ctx *ctx, int path);
 
+/* Kernel classes of vpm_set_tuning: rollouts whose wake fits a quarter of a
+ * CU's LDS run in 4-wave workgroups (several per CU), larger ones in one
+ * 16-wave workgroup per CU, and wakes beyond the LDS stream from the
+ * workspace. */
+#define VPM_CLASS_SMALL 0
+#define VPM_CLASS_LARGE 1
+#define VPM_CLASS_STREAM 2
+
+/* FP32 kernel shape of one class for later calls on this context (results
+ * change only by rounding): targets_per_thread in {1, 2, 4} is how many
+ * targets each lane holds in registers against each LDS source read, and
+ * tile in {64, 128, 256} how many sources are summed plainly before each
+ * compensated (TwoSum) fold. Defaults: small 4/64, large 2/64, streamed
+ * 4/64. FP64 keeps 2/64. The project's autotuner (the Python module
+ * paper_2509_16079_amd.autotune) picks these by timing. A larger target count
+ * in the large class lowers its LDS capacity, moving the streamed-class
+ * boundary. Errors: VPM_EINVAL. */
+VPM_API int vpm_set_tuning(vpm_ctx *ctx, int32_t kernel_class,
+                           int32_t targets_per_thread, int32_t tile);
+VPM_API int vpm_get_tuning(const vpm_ctx *ctx, int32_t kernel_class,
+                           int32_t *targets_per_thread, int32_t *tile);
+
 /* Message of the calling thread's last error ("" if none). */
 VPM_API const char *vpm_last_error(void);
 

@@ -167,6 +167,30 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
                              static_cast<hipStream_t>(stream));
 }
 
+VPM_API int vpm_set_tuning(vpm_ctx *ctx, int32_t kernel_class, int32_t targets_per_thread,
+                           int32_t tile) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  if (kernel_class < VPM_CLASS_SMALL || kernel_class > VPM_CLASS_STREAM)
+    return fail(VPM_EINVAL, "unknown kernel class");
+  if (targets_per_thread != 1 && targets_per_thread != 2 && targets_per_thread != 4)
+    return fail(VPM_EINVAL, "targets_per_thread must be 1, 2 or 4");
+  if (tile != 64 && tile != 128 && tile != 256)
+    return fail(VPM_EINVAL, "tile must be 64, 128 or 256");
+  std::lock_guard<std::mutex> lock(ctx->ws_mu);
+  ctx->tune[kernel_class] = vpm::Tune{targets_per_thread, tile};
+  return VPM_OK;
+}
+
+VPM_API int vpm_get_tuning(const vpm_ctx *ctx, int32_t kernel_class,
+                           int32_t *targets_per_thread, int32_t *tile) {
+  if (!ctx || !targets_per_thread || !tile) return fail(VPM_EINVAL, "NULL argument");
+  if (kernel_class < VPM_CLASS_SMALL || kernel_class > VPM_CLASS_STREAM)
+    return fail(VPM_EINVAL, "unknown kernel class");
+  *targets_per_thread = ctx->tune[kernel_class].tmax;
+  *tile = ctx->tune[kernel_class].tile;
+  return VPM_OK;
+}
+
 VPM_API int vpm_reserve(vpm_ctx *ctx, const vpm_params *params, int32_t K, int32_t H,
                         int32_t max_wake0, int32_t n_fields) {
   if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");

@@ -39,7 +39,6 @@
 namespace vpm {
 namespace {
 
-constexpr int kTile = 64;          // sources per compensation tile
 constexpr int kStreamTile = 1024;  // sources per LDS stage (streaming kernel)
 constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
 constexpr double kTwoPi = 6.28318530717958647692528676655900577;
@@ -153,14 +152,14 @@ __device__ inline void fold_tile(R (&sx)[T], R (&sz)[T], R (&cx)[T], R (&cz)[T],
 }
 
 // Sources [s_lo, s_hi) of `src` onto the T targets of this lane, folded
-// every 64 sources.
-template <typename R, int T>
+// every TILE sources.
+template <typename R, int T, int TILE>
 __device__ inline void accumulate(const typename SrcOf<R>::type *__restrict__ src,
                                   int s_lo, int s_hi, const R (&tx)[T],
                                   const R (&tz)[T], R rc4, R (&sx)[T], R (&sz)[T],
                                   R (&cx)[T], R (&cz)[T]) {
-  for (int s0 = s_lo; s0 < s_hi; s0 += kTile) {
-    const int s1 = min(s0 + kTile, s_hi);
+  for (int s0 = s_lo; s0 < s_hi; s0 += TILE) {
+    const int s1 = min(s0 + TILE, s_hi);
     R ax[T], az[T];
 #pragma unroll
     for (int j = 0; j < T; ++j) ax[j] = az[j] = R(0);
@@ -644,7 +643,7 @@ __device__ inline int claim(const Queue &q, Shared<R> &sh, int tid,
 
 // ---------------------------------------------------------------- LDS path
 
-template <typename R, int T, int NW>
+template <typename R, int T, int NW, int TILE>
 __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
                                  const typename SrcOf<R>::type *src, Vec2<R> *red,
                                  int c0, int NT, int head, int s_lo, int s_hi,
@@ -656,7 +655,7 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
     target_pos(a, sh, src, c0 + lane + 64 * j, NT, head, tx[j], tz[j]);
     sx[j] = sz[j] = cx[j] = cz[j] = R(0);
   }
-  accumulate<R, T>(src, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
+  accumulate<R, T, TILE>(src, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
   Vec2<R> *out = red + wave * 64 * T;
 #pragma unroll
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
@@ -666,7 +665,7 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
 // l / r of g = 64 / r equal parts of this wave's sources, so g r lanes work
 // instead of r. The partials land where a T = 1 chunk puts them, lane l at
 // red[wave 64 + l], and are added per target over waves, then parts.
-template <typename R, int NW>
+template <typename R, int NW, int TILE>
 __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
                                 const typename SrcOf<R>::type *src, Vec2<R> *red,
                                 int c0, int NT, int head, int s_lo, int s_hi,
@@ -677,7 +676,7 @@ __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
   target_pos(a, sh, src, c0 + t, NT, head, tx[0], tz[0]);
   if (q < g) {
     const int len = s_hi - s_lo;
-    accumulate<R, 1>(src, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
+    accumulate<R, 1, TILE>(src, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
                      sx, sz, cx, cz);
   }
   red[wave * 64 + lane] = Vec2<R>{sx[0] + cx[0], sz[0] + cz[0]};
@@ -707,7 +706,7 @@ __device__ inline int simd_id() {
 // LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
-template <typename R, int TMAX, int MINW, int NW>
+template <typename R, int TMAX, int MINW, int NW, int TILE>
 __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
@@ -748,12 +747,12 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         while (T > 1 && 64 * T > rem) T >>= 1;
         const int tail = rem < 32 ? rem : 0;  // tails of 32..63 keep a lane each
         if (tail) {
-          lds_pass_a_tail<R, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
+          lds_pass_a_tail<R, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
         } else {
           switch (T) {
-            case 1: lds_pass_a_chunk<R, 1, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 1: lds_pass_a_chunk<R, 1, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
           }
         }
         __syncthreads();
@@ -793,7 +792,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 
 // ---------------------------------------------------------- streaming path
 
-template <typename R, int T, int NW>
+template <typename R, int T, int NW, int TILE>
 __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
                                     const typename SrcOf<R>::type *src,
                                     typename SrcOf<R>::type *tile, Vec2<R> *vel,
@@ -812,7 +811,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
     const int cnt = min(kStreamTile, n_w - s0);
     for (int q = tid; q < cnt; q += 64 * NW) tile[q] = src[head + s0 + q];
     __syncthreads();
-    accumulate<R, T>(tile, 0, cnt, tx, tz, rc4, sx, sz, cx, cz);
+    accumulate<R, T, TILE>(tile, 0, cnt, tx, tz, rc4, sx, sz, cx, cz);
     __syncthreads();
   }
 #pragma unroll
@@ -830,7 +829,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
 // Persistent: each workgroup keeps its rollout's wake in workspace slot
 // blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
 // or, with a queue, claims them in planned order.
-template <typename R, int TMAX, int NW>
+template <typename R, int TMAX, int NW, int TILE>
 __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
@@ -872,9 +871,9 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
         int T = TMAX;
         while (T > 1 && 64 * NW * T > rem) T >>= 1;
         switch (T) {
-          case 1: stream_pass_a_round<R, 1, NW>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
-          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
-          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 1: stream_pass_a_round<R, 1, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
         }
         c0 += 64 * NW * T;
       }
@@ -990,7 +989,7 @@ int set_lds(Kern kern, int bytes) {
 
 // Launch the LDS kernel for wakes up to `cap` vortices; grid = `grid`
 // workgroups (one per rollout without a queue).
-template <typename R, int TMAX, int MINW, int NW>
+template <typename R, int TMAX, int MINW, int NW, int TILE>
 int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
                hipStream_t stream) {
   a.cap = cap;
@@ -998,7 +997,7 @@ int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
                                    " does not fit the LDS-resident kernel");
-  auto kern = rollout_lds_kernel<R, TMAX, MINW, NW>;
+  auto kern = rollout_lds_kernel<R, TMAX, MINW, NW, TILE>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a, qu);
@@ -1029,13 +1028,13 @@ int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what,
   return VPM_OK;
 }
 
-template <typename R, int TMAX, int NW>
+template <typename R, int TMAX, int NW, int TILE>
 int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
                   hipStream_t stream, bool capturing) {
   const int lds = stream_layout<R>(a.nb, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
-  auto kern = rollout_stream_kernel<R, TMAX, NW>;
+  auto kern = rollout_stream_kernel<R, TMAX, NW, TILE>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
@@ -1056,6 +1055,57 @@ int lds_capacity(int nb, int S, int nw, int tmax, size_t bytes) {
   return bytes > fixed ? static_cast<int>((bytes - fixed) / lds_per_vortex<R>()) : 0;
 }
 
+// Kernel instance for a class's tuning (targets per thread x compensation
+// tile). FP32 compiles every pair of {1, 2, 4} x {64, 128, 256}; FP64 only
+// its fixed shape (2 targets per thread, 64-source tiles).
+template <typename R, int MINW, int NW>
+int launch_lds_tuned(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
+                     hipStream_t stream, Tune t) {
+  if constexpr (sizeof(R) == 8) {
+    return launch_lds<R, 2, MINW, NW, 64>(ctx, a, cap, grid, qu, stream);
+  } else {
+    switch (t.tmax * 1000 + t.tile) {
+      case 1064: return launch_lds<R, 1, MINW, NW, 64>(ctx, a, cap, grid, qu, stream);
+      case 1128: return launch_lds<R, 1, MINW, NW, 128>(ctx, a, cap, grid, qu, stream);
+      case 1256: return launch_lds<R, 1, MINW, NW, 256>(ctx, a, cap, grid, qu, stream);
+      case 2064: return launch_lds<R, 2, MINW, NW, 64>(ctx, a, cap, grid, qu, stream);
+      case 2128: return launch_lds<R, 2, MINW, NW, 128>(ctx, a, cap, grid, qu, stream);
+      case 2256: return launch_lds<R, 2, MINW, NW, 256>(ctx, a, cap, grid, qu, stream);
+      case 4064: return launch_lds<R, 4, MINW, NW, 64>(ctx, a, cap, grid, qu, stream);
+      case 4128: return launch_lds<R, 4, MINW, NW, 128>(ctx, a, cap, grid, qu, stream);
+      case 4256: return launch_lds<R, 4, MINW, NW, 256>(ctx, a, cap, grid, qu, stream);
+      default: return fail(VPM_EINVAL, "unsupported kernel tuning");
+    }
+  }
+}
+
+template <typename R, int NW>
+int launch_stream_tuned(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu, hipStream_t stream,
+                        bool capturing, Tune t) {
+  if constexpr (sizeof(R) == 8) {
+    return launch_stream<R, 2, NW, 64>(ctx, a, grid, qu, stream, capturing);
+  } else {
+    switch (t.tmax * 1000 + t.tile) {
+      case 1064: return launch_stream<R, 1, NW, 64>(ctx, a, grid, qu, stream, capturing);
+      case 1128: return launch_stream<R, 1, NW, 128>(ctx, a, grid, qu, stream, capturing);
+      case 1256: return launch_stream<R, 1, NW, 256>(ctx, a, grid, qu, stream, capturing);
+      case 2064: return launch_stream<R, 2, NW, 64>(ctx, a, grid, qu, stream, capturing);
+      case 2128: return launch_stream<R, 2, NW, 128>(ctx, a, grid, qu, stream, capturing);
+      case 2256: return launch_stream<R, 2, NW, 256>(ctx, a, grid, qu, stream, capturing);
+      case 4064: return launch_stream<R, 4, NW, 64>(ctx, a, grid, qu, stream, capturing);
+      case 4128: return launch_stream<R, 4, NW, 128>(ctx, a, grid, qu, stream, capturing);
+      case 4256: return launch_stream<R, 4, NW, 256>(ctx, a, grid, qu, stream, capturing);
+      default: return fail(VPM_EINVAL, "unsupported kernel tuning");
+    }
+  }
+}
+
+// The tuning a class runs with in precision R (FP64 shapes are fixed).
+template <typename R> Tune class_tune(const vpm_ctx *ctx, int cls) {
+  if constexpr (sizeof(R) == 8) return Tune{2, 64};
+  return ctx->tune[cls];
+}
+
 // One batch in a given precision. Uniform batches (one field) run one
 // rollout per workgroup on the caller's stream. Uneven batches are planned
 // on the device and run as up to three persistent class kernels on forked
@@ -1063,7 +1113,7 @@ int lds_capacity(int nb, int S, int nw, int tmax, size_t bytes) {
 // context's workspace are ordered by an event; while the caller's stream is
 // being captured into a graph that ordering is the caller's (replays of a
 // graph and other calls on the same context must not overlap).
-template <typename R, int TMAX_S, int MINW_S, int TMAX_L, int TMAX_X, int NW_X>
+template <typename R, int MINW_S, int NW_X>
 int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
   hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
   VPM_HIP_TRY(hipStreamIsCapturing(stream, &cap_status));
@@ -1071,15 +1121,17 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
   // FP32 takes 16-wave large-class workgroups (128 VGPRs each), FP64 8
   constexpr int kNwSmall = 4, kNwLarge = sizeof(R) == 4 ? 16 : 8;
   const int cap = a.cap;  // max_wake0 + 2H
-  const int cap_small = lds_capacity<R>(a.nb, a.S, kNwSmall, TMAX_S, ctx->max_lds / 4);
-  const int cap_large = lds_capacity<R>(a.nb, a.S, kNwLarge, TMAX_L, ctx->max_lds);
+  const Tune t_s = class_tune<R>(ctx, VPM_CLASS_SMALL), t_l = class_tune<R>(ctx, VPM_CLASS_LARGE);
+  const Tune t_x = class_tune<R>(ctx, VPM_CLASS_STREAM);
+  const int cap_small = lds_capacity<R>(a.nb, a.S, kNwSmall, t_s.tmax, ctx->max_lds / 4);
+  const int cap_large = lds_capacity<R>(a.nb, a.S, kNwLarge, t_l.tmax, ctx->max_lds);
   const Queue none{nullptr, nullptr, nullptr, 0};
   const bool stream_only = path == VPM_PATH_STREAM;
   if (a.n_fields == 1 || path == VPM_PATH_LDS || stream_only) {
     if (!stream_only && cap <= cap_small)
-      return launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream);
+      return launch_lds_tuned<R, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream, t_s);
     if (!stream_only && cap <= cap_large)
-      return launch_lds<R, TMAX_L, 1, kNwLarge>(ctx, a, cap, a.K, none, stream);
+      return launch_lds_tuned<R, 1, kNwLarge>(ctx, a, cap, a.K, none, stream, t_l);
     if (path == VPM_PATH_LDS)
       return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
                                      " does not fit the LDS-resident kernel");
@@ -1087,7 +1139,7 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
     if (ctx->ws_event_valid && !capturing)
       VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
     const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
-    int rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, none, stream, capturing);
+    int rc = launch_stream_tuned<R, NW_X>(ctx, a, grid, none, stream, capturing, t_x);
     if (rc != VPM_OK) return rc;
     if (!capturing) {
       VPM_HIP_TRY(hipEventRecord(ctx->ws_event, stream));
@@ -1118,7 +1170,8 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
     hipStream_t s = ctx->side[0];
     VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
     const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
-    rc = launch_stream<R, TMAX_X, NW_X>(ctx, a, grid, Queue{list, next, range, 0}, s, capturing);
+    rc = launch_stream_tuned<R, NW_X>(ctx, a, grid, Queue{list, next, range, 0}, s, capturing,
+                                      t_x);
     if (rc != VPM_OK) return rc;
     VPM_HIP_TRY(hipEventRecord(ctx->join_event[0], s));
     joins[n_join++] = ctx->join_event[0];
@@ -1129,7 +1182,7 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
     VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
     const int c1 = cap < cap_large ? cap : cap_large;
     const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
-    rc = launch_lds<R, TMAX_L, 1, kNwLarge>(ctx, a, c1, grid, Queue{list, next, range, 1}, s);
+    rc = launch_lds_tuned<R, 1, kNwLarge>(ctx, a, c1, grid, Queue{list, next, range, 1}, s, t_l);
     if (rc != VPM_OK) return rc;
     VPM_HIP_TRY(hipEventRecord(ctx->join_event[1], s));
     joins[n_join++] = ctx->join_event[1];
@@ -1140,7 +1193,8 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
     VPM_HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event, 0));
     const int c2 = cap < cap_small ? cap : cap_small;
     const int grid = a.K < 4 * ctx->n_cu ? a.K : 4 * ctx->n_cu;
-    rc = launch_lds<R, TMAX_S, MINW_S, kNwSmall>(ctx, a, c2, grid, Queue{list, next, range, 2}, s);
+    rc = launch_lds_tuned<R, MINW_S, kNwSmall>(ctx, a, c2, grid, Queue{list, next, range, 2}, s,
+                                               t_s);
     if (rc != VPM_OK) return rc;
     VPM_HIP_TRY(hipEventRecord(ctx->join_event[2], s));
     joins[n_join++] = ctx->join_event[2];
@@ -1157,10 +1211,11 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 
 // Grow the context buffers that a batch of these sizes would need (the same
 // class decisions as run_batch), outside any stream capture.
-template <typename R, int TMAX_L>
+template <typename R>
 int reserve_batch(vpm_ctx *ctx, int nb, int K, int cap, int n_fields) {
   constexpr int kNwLarge = sizeof(R) == 4 ? 16 : 8;
-  const int cap_large = lds_capacity<R>(nb, nb + 2, kNwLarge, TMAX_L, ctx->max_lds);
+  const int cap_large =
+      lds_capacity<R>(nb, nb + 2, kNwLarge, class_tune<R>(ctx, VPM_CLASS_LARGE).tmax, ctx->max_lds);
   const int path = ctx->path;
   std::lock_guard<std::mutex> lock(ctx->ws_mu);
   if (path == VPM_PATH_STREAM || (path == VPM_PATH_AUTO && cap > cap_large)) {
@@ -1181,8 +1236,8 @@ int reserve_batch(vpm_ctx *ctx, int nb, int K, int cap, int n_fields) {
 int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wake0,
                     int n_fields) {
   const int cap = max_wake0 + 2 * H;
-  if (p->precision == VPM_FP64) return reserve_batch<double, 2>(ctx, p->n_bound, K, cap, n_fields);
-  return reserve_batch<float, 2>(ctx, p->n_bound, K, cap, n_fields);
+  if (p->precision == VPM_FP64) return reserve_batch<double>(ctx, p->n_bound, K, cap, n_fields);
+  return reserve_batch<float>(ctx, p->n_bound, K, cap, n_fields);
 }
 
 int lds_resident_capacity(int nb) {
@@ -1250,8 +1305,8 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.vel_last = wake ? out->vel_last : nullptr;
   a.n_vel_last = out->n_vel_last;
   if (p->precision == VPM_FP64)
-    return run_batch<double, 2, 2, 2, 2, 8>(ctx, a, ctx->path, stream);
-  return run_batch<float, 4, 4, 2, 4, 16>(ctx, a, ctx->path, stream);
+    return run_batch<double, 2, 8>(ctx, a, ctx->path, stream);
+  return run_batch<float, 4, 16>(ctx, a, ctx->path, stream);
 }
 
 }  // namespace vpm

@@ -43,6 +43,12 @@ inline int first_row(int mode) { return mode == VPM_SHED_BOTH ? 0 : 1; }
 int plate_inverse_T(int nb, double chord, double shed_frac, double r_core,
                     int mode, std::vector<double> &inv_t);
 
+// FP32 kernel shape of one class: targets per thread (pass-A register
+// blocking) and sources per compensated tile.
+struct Tune {
+  int tmax, tile;
+};
+
 struct PlateKey {
   int nb, mode;
   double chord, shed_frac, r_core;
@@ -59,6 +65,8 @@ struct vpm_ctx {
   int max_lds = 65536;      // dynamic LDS bytes one workgroup may use
   int n_cu = 0;
   int path = VPM_PATH_AUTO; // kernel variant selection (vpm_set_path)
+  // FP32 shape per kernel class (vpm_set_tuning): small, large, streamed
+  vpm::Tune tune[3] = {{4, 64}, {2, 64}, {4, 64}};
   std::mutex mu;
   std::map<vpm::PlateKey, double *> plate_cache;  // device inverses
   // streaming-kernel workspace, shared by calls on this context; each launch

@@ -21,6 +21,8 @@ ROLLOUT_NONFINITE, ROLLOUT_CAPACITY, ROLLOUT_BADFIELD = 1, 2, 4
 SHED_BOTH, SHED_TE, SHED_NONE = 0, 1, 2
 FP32C, FP64 = 0, 1
 PATH_AUTO, PATH_LDS, PATH_STREAM = 0, 1, 2
+CLASS_SMALL, CLASS_LARGE, CLASS_STREAM = 0, 1, 2
+CLASS_NAMES = {CLASS_SMALL: "small", CLASS_LARGE: "large", CLASS_STREAM: "stream"}
 
 _P = C.c_void_p
 _D = C.c_double
@@ -68,6 +70,8 @@ def lib():
         L.mppi_weights.argtypes = [_P, _I, _I, _P, _D, _P, _P, _P, _P, _P, _P, _P]
         L.vpm_set_path.argtypes = [_P, C.c_int]
         L.vpm_reserve.argtypes = [_P, C.POINTER(Params), _I, _I, _I, _I]
+        L.vpm_set_tuning.argtypes = [_P, _I, _I, _I]
+        L.vpm_get_tuning.argtypes = [_P, _I, C.POINTER(_I), C.POINTER(_I)]
         L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
         L.vpm_pair_count.restype = C.c_int64
         _lib = L
@@ -235,6 +239,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tuning(self, kernel_class: int, targets_per_thread: int, tile: int):
+        """FP32 kernel shape of one class (``vpm_set_tuning``)."""
+        check(lib().vpm_set_tuning(self.h, int(kernel_class), int(targets_per_thread), int(tile)),
+              "vpm_set_tuning")
+
+    def get_tuning(self, kernel_class: int):
+        t, tile = _I(), _I()
+        check(lib().vpm_get_tuning(self.h, int(kernel_class), C.byref(t), C.byref(tile)),
+              "vpm_get_tuning")
+        return t.value, tile.value
 
     def reserve(self, params: dict, K, H, max_wake0, n_fields=1, precision=FP32C):
         """``vpm_reserve``: size the context so that later batches no larger

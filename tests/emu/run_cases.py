@@ -40,13 +40,24 @@ def cases():
         "uneven": lambda: W.uneven_batch(K=6, H=3, n_min=1, n_max=700),
         # counts 1100..7000: large class with 128-target tasks and streamed rollouts
         "large": lambda: W.uneven_batch(K=5, H=2, n_min=1100, n_max=7000),
+        # the same with non-default kernel shapes in every class
+        "large_tuned": lambda: W.uneven_batch(K=5, H=2, n_min=1100, n_max=7000),
     }
+
+
+TUNINGS = {"large_tuned": [(V.CLASS_SMALL, 1, 256), (V.CLASS_LARGE, 4, 128),
+                           (V.CLASS_STREAM, 2, 256)]}
 
 
 def main(names):
     ctx = V.Context(0)
     for name in names:
         wl = cases()[name]()
+        for cls in (V.CLASS_SMALL, V.CLASS_LARGE, V.CLASS_STREAM):
+            ctx.set_tuning(cls, *{V.CLASS_SMALL: (4, 64), V.CLASS_LARGE: (2, 64),
+                                  V.CLASS_STREAM: (4, 64)}[cls])
+        for cls, t, tile in TUNINGS.get(name, []):
+            ctx.set_tuning(cls, t, tile)
         o = run_oracle(wl, traj=True, final_wake=True, gamma_s=True)
         for prec in (V.FP32C, V.FP64):
             db = V.DeviceBatch(wl, device="cpu")

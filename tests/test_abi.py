@@ -109,3 +109,10 @@ def test_package_never_touches_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.lower() or f == "workloads.py", f
                 assert "vpm_oracle" not in txt, f
+
+
+def test_tuning_arguments_are_checked_without_a_gpu():
+    L = V.lib()
+    t, tile = C.c_int32(), C.c_int32()
+    assert L.vpm_set_tuning(None, 0, 4, 64) == V.EINVAL
+    assert L.vpm_get_tuning(None, 0, C.byref(t), C.byref(tile)) == V.EINVAL

@@ -64,3 +64,24 @@ def test_uneven_full_size_horizon(ctx):
     e = rel_l2(g["traj"][idx], o["traj"])
     assert e <= 1e-4, describe("uneven 4096 H15 traj", err=e)
     assert np.all(g["status"] == 0)
+
+
+@pytest.mark.parametrize("shape", [(1, 64), (1, 256), (2, 128), (4, 64), (4, 256)])
+def test_every_kernel_shape_matches_oracle(ctx, shape):
+    """The autotuner's shapes (targets per thread x compensated tile), set
+    for all three classes, on a batch that reaches all three."""
+    wl = W.uneven_batch(K=24, H=2, n_min=10, n_max=7000)
+    try:
+        for cls in (V.CLASS_SMALL, V.CLASS_LARGE, V.CLASS_STREAM):
+            ctx.set_tuning(cls, *shape)
+        g = V.run_workload(ctx, wl, V.FP32C, vel_last=True)
+    finally:
+        ctx.set_tuning(V.CLASS_SMALL, 4, 64)
+        ctx.set_tuning(V.CLASS_LARGE, 2, 64)
+        ctx.set_tuning(V.CLASS_STREAM, 4, 64)
+    o = run_oracle(wl, vel_last=True)
+    assert np.all(g["status"] == 0)
+    for k in range(wl.K):
+        e = rel_l2(vel_segment(g, k), vel_segment(o, k))
+        assert e <= TOL[V.FP32C], describe("shape %s k=%d" % (shape, k), err=e)
+    assert rel_l2(g["g_final"], o["g_final"]) <= TOL[V.FP32C]

@@ -26,7 +26,7 @@ def emu_lib():
     return r.stdout.strip()
 
 
-@pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large"])
+@pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large", "large_tuned"])
 def test_emulated_kernels_match_oracle(emu_lib, case):
     try:
         r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), case],
