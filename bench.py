@@ -210,17 +210,23 @@ def apply_tuning(ctx, path):
 
 
 def gpu_clock():
-    """Current shader and memory clocks as rocm-smi reports them (read after
-    the timed region; None if the tool is unavailable)."""
-    import subprocess
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
-                           text=True, timeout=20)
-        d = json.loads(r.stdout)
-        card = d[sorted(d)[0]]
-        return {k: v for k, v in card.items() if "sclk" in k.lower() or "mclk" in k.lower()}
-    except Exception:
-        return None
+    """Current shader and memory clock levels from the driver's sysfs tables
+    (the entry marked '*'), read after the timed region; None if absent.
+    A file read, not a tool: nothing is spawned inside the GPU process."""
+    import glob
+    out = {}
+    for card in sorted(glob.glob("/sys/class/drm/card*/device")):
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk"):
+            try:
+                for line in open(os.path.join(card, name)):
+                    if line.rstrip().endswith("*"):
+                        out[name[7:]] = line.split(":", 1)[1].strip(" *\n")
+            except OSError:
+                continue
+        if out:
+            out["card"] = os.path.basename(os.path.dirname(card))
+            return out
+    return None
 
 
 def cpu_model():

@@ -115,11 +115,13 @@ __device__ inline void reg_term(R dx, R dz, R g, R rc4, R &vx, R &vz) {
 }
 
 // Singular kernel (Eq. 4) times Gamma, g = Gamma/(2 pi): g (-dz, dx) / r^2.
-// A coincident point has dx = dz = 0 and a finite k, so it contributes 0.
+// The smallest normal number is added inside the r^2 FMA chain, so a
+// coincident point has a finite k and contributes exactly 0, while any r^2
+// above ~1e-30 (FP32) rounds exactly as without it.
 template <typename R>
 __device__ inline void sing_term(R dx, R dz, R g, R &vx, R &vz) {
-  R r2 = dx * dx + dz * dz;
-  R k = g * rcp(fmax(r2, tiny(r2)));
+  R r2 = fma(dz, dz, fma(dx, dx, tiny(dx)));
+  R k = g * rcp(r2);
   vx -= dz * k;
   vz += dx * k;
 }
@@ -718,7 +720,10 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
   Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(lds + a.off_vel);
   double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar (every lane is active here), so loops bounded by
+  // it are counted in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_surf = 2 * a.nb + 3;
   for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
   if (tid == 0) sh.slot = simd_id();
@@ -841,7 +846,10 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
   Src *src = reinterpret_cast<Src *>(a.ws_src) + (size_t)blockIdx.x * a.cap;
   Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(a.ws_vel) + (size_t)blockIdx.x * a.cap;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar (every lane is active here), so loops bounded by
+  // it are counted in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_surf = 2 * a.nb + 3;
   for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
 
