@@ -91,10 +91,33 @@ template <typename R> struct Shared {
   long long pairs;
 };
 
+// Value of v in lane j (uniform j) for every lane: two readlanes, no LDS.
+__device__ inline double bcast(double v, int j) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(u), j);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(u >> 32), j);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// v from another lane of the same 16-lane row, by DPP control CTRL.
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(static_cast<long long>(
+      (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo)));
+}
+
+// Sum of v over the 64 lanes (all active), in every lane, in a fixed order:
+// pairs, quads, then 8- and 16-lane rows by DPP (no LDS), then the four row
+// sums as (r0 + r1) + (r2 + r3).
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x128>(v);  // row_ror:8
+  return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
 }
 
 __device__ inline float rsq(float d) { return __builtin_amdgcn_rsqf(d); }
@@ -332,7 +355,7 @@ template <typename R>
 __device__ __forceinline__ void solve_section(
     const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *src, Vec2<R> *vel,
     const double2 *vsurf, const double *kinv, int k, int n, int head, int n_w,
-    int lane) {
+    int lane, double u_n) {
   using Src = typename SrcOf<R>::type;
   const int nb = a.nb, S = a.S, nc = nb + 1;
   const double dt = a.dt, lb = a.chord / nb;
@@ -382,9 +405,7 @@ __device__ __forceinline__ void solve_section(
       }
     }
   }
-  auto row = [&](int r) -> double {
-    return r < 64 ? __shfl(gam0, r, 64) : __shfl(gam1, r - 64, 64);
-  };
+  auto row = [&](int r) -> double { return r < 64 ? bcast(gam0, r) : bcast(gam1, r - 64); };
   const double glev = row(nb), gtev = row(nb + 1);
   if (a.gamma_s) {
     double *gs = a.gamma_s + ((size_t)k * a.H + n) * S;
@@ -423,7 +444,7 @@ __device__ __forceinline__ void solve_section(
     // Sec. III-B: elevator force and rigid-body accelerations
     const R x = sh.g[0], z = sh.g[1], th = sh.g[2], ph = sh.g[3];
     const R xd = sh.g[4], zd = sh.g[5], thr = sh.g[6];
-    const R u = R(a.u_mean[n] + a.u_eps[(size_t)k * a.H + n]);
+    const R u = R(u_n);
     const R l = R(a.l_body), le = R(a.l_elev);
     const R ct = sh.ct, st = sh.st, ctp = cos(th + ph), stp = sin(th + ph);
     const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
@@ -743,6 +764,12 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       rotate_priority(sh.slot, n);
       const int head = sh.head, n_w = sh.n_w;
       const int NT = n_surf + n_w;
+      // this step's control, loaded now so its latency hides behind pass A
+      double u_m = 0.0, u_e = 0.0;
+      if (tid == 0) {
+        u_m = a.u_mean[n];
+        u_e = a.u_eps[(size_t)k * a.H + n];
+      }
 
       const int s_lo = head + (n_w * wave) / NW;
       const int s_hi = head + (n_w * (wave + 1)) / NW;
@@ -783,7 +810,8 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         c0 += span;
       }
 
-      if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
+      if (wave == 0)
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e);
       __syncthreads();
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
@@ -873,6 +901,11 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       }
       const int head = sh.head, n_w = sh.n_w;
       const int NT = n_surf + n_w;
+      double u_m = 0.0, u_e = 0.0;  // this step's control, loaded before pass A
+      if (tid == 0) {
+        u_m = a.u_mean[n];
+        u_e = a.u_eps[(size_t)k * a.H + n];
+      }
       // pass A in rounds of 64 * NW * T targets (T shrinks for the tail)
       for (int c0 = 0; c0 < NT;) {
         const int rem = NT - c0;
@@ -886,7 +919,8 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
         c0 += 64 * NW * T;
       }
       __syncthreads();
-      if (wave == 0) solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane);
+      if (wave == 0)
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e);
       __syncthreads();
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
