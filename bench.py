@@ -46,6 +46,8 @@ def parse():
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="also replay the serving requests at 0.25/0.5/0.8 of capacity")
     ap.add_argument("--tuning", default=None,
                     help="kernel-shape table written by paper_2509_16079_amd.autotune "
                          "(default: the packaged table if present; 'none': library defaults)")
@@ -280,10 +282,12 @@ def error_vs_oracle(V, ctx, sub, o, prec, horizon_note):
     }
 
 
-def serving(n_requests):
+def serving(n_requests, sweep=False):
     """Replay the first requests of the serving trace (Poisson arrivals at
     100 req/s, K~U{256..2048}, H~U{50..200}, 16 resident states of
-    500..6000 vortices) through the service and through the plain path."""
+    500..6000 vortices) through the service and through the plain path.
+    With `sweep`, also replay them at offered loads of 0.25, 0.5 and 0.8 of
+    the capacity measured in the saturated replay (arrival gaps stretched)."""
     from paper_2509_16079_amd import vpm as V
     from paper_2509_16079_amd import workloads as W
     params, states, reqs = W.serving_trace()
@@ -292,7 +296,7 @@ def serving(n_requests):
     dt = float(W.f32(0.005))
     g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
 
-    def replay(slots):
+    def replay(slots, stretch=1.0):
         p = V.Planner(max_slots=slots, budget_bytes=64 << 30)
         try:
             sids = [p.put_state(*s, g0, np.zeros(32)) for s in states]
@@ -302,7 +306,8 @@ def serving(n_requests):
             t_start = time.perf_counter()
             tickets = []
             for r, e in zip(reqs, eps):
-                delay = t_start + r.t_arrive - reqs[0].t_arrive - time.perf_counter()
+                delay = (t_start + stretch * (r.t_arrive - reqs[0].t_arrive)
+                         - time.perf_counter())
                 if delay > 0:
                     time.sleep(delay)
                 tickets.append(p.submit(sids[r.state], params, np.zeros(r.H), e, dt))
@@ -320,12 +325,26 @@ def serving(n_requests):
 
     served = replay(8)
     plain = replay(1)
-    return {"requests": len(reqs), "trace": "first %d requests of the seeded 100 req/s "
-            "trace (K~U{256..2048}, H~U{50..200}, resident states of 500..6000 vortices)"
-            % len(reqs),
-            "served_8_slots": served, "plain_one_at_a_time": plain,
-            "p99_speedup": plain["p99_ms"] / served["p99_ms"],
-            "rollouts_speedup": served["rollouts_per_s"] / plain["rollouts_per_s"]}
+    out = {"requests": len(reqs), "trace": "first %d requests of the seeded 100 req/s "
+           "trace (K~U{256..2048}, H~U{50..200}, resident states of 500..6000 vortices)"
+           % len(reqs),
+           "served_8_slots": served, "plain_one_at_a_time": plain,
+           "p99_speedup": plain["p99_ms"] / served["p99_ms"],
+           "rollouts_speedup": served["rollouts_per_s"] / plain["rollouts_per_s"]}
+    if sweep:
+        # capacity in requests/s from the saturated replay; the trace offers
+        # len(reqs) requests over its arrival span
+        cap = len(reqs) / max(served["makespan_s"], plain["makespan_s"])
+        offered = (len(reqs) - 1) / max(reqs[-1].t_arrive - reqs[0].t_arrive, 1e-9)
+        out["capacity_req_per_s"] = cap
+        out["sweep"] = []
+        for f in (0.25, 0.5, 0.8):
+            stretch = offered / (f * cap)
+            s8, s1 = replay(8, stretch), replay(1, stretch)
+            out["sweep"].append({"load": f, "served_8_slots": s8, "plain_one_at_a_time": s1,
+                                 "p99_speedup": s1["p99_ms"] / s8["p99_ms"]})
+            print("serving sweep load %.2f done" % f, file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -454,7 +473,7 @@ def main():
     if n_serve is None:
         n_serve = 16 if args.workload == "realtime" else 0
     if n_serve > 0:
-        line["serving"] = serving(n_serve)
+        line["serving"] = serving(n_serve, sweep=args.serving_sweep)
     if not args.no_cpu_baseline:
         base, sub, o = cpu_baseline(args.workload, wl)
         line["cpu_baseline"] = base
