@@ -44,6 +44,9 @@ class Params(C.Structure):
         ("l_wing", C.c_double),
         ("l_elev", C.c_double),
         ("s_elev", C.c_double),
+        ("alpha_crit", C.c_double),
+        ("gate", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 
@@ -111,7 +114,8 @@ def _f64(a):
 def make_params(d: dict) -> Params:
     p = Params()
     for name, _ in Params._fields_:
-        setattr(p, name, d[name])
+        if name != "pad_":
+            setattr(p, name, d.get(name, 0) if name in ("gate", "alpha_crit") else d[name])
     return p
 
 

@@ -484,11 +484,22 @@ typedef struct {
  * body accelerations, shedding, wake velocities, advection and decay,
  * merging, glider Euler step. gamma_s_out (S values) and vel (2 * (n_w + 2)
  * values) may be NULL. */
+double orc_wing_aoa(const orc_params *p, const double *g) {
+  /* wing point x_w = x - l_w e_f; its velocity, differentiated in time */
+  const double xd_w = g[4] + p->l_wing * g[6] * sin(g[2]);
+  const double zd_w = g[5] - p->l_wing * g[6] * cos(g[2]);
+  return g[2] - atan2(zd_w, xd_w);
+}
+
 static void orc_step(const orc_params *p, orc_state *s, double dt, double u,
                      int32_t reverse, double *gamma_s_out, orc_loads *ld,
                      double *vel, int32_t *n_vel) {
   const int32_t nb = p->n_bound;
-  const int32_t mode = p->shed_mode;
+  /* Sec. III-A: with the separation gate the leading edge sheds only while
+   * the wing is beyond the critical angle; the trailing edge always does. */
+  const int32_t mode = !p->gate ? p->shed_mode
+                       : orc_wing_aoa(p, s->g) > p->alpha_crit ? ORC_SHED_BOTH
+                                                                : ORC_SHED_TE;
   const int32_t S = orc_system_size(nb, mode);
   const double lb = p->chord / nb;
   double *g = s->g;

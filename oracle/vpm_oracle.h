@@ -48,7 +48,16 @@ typedef struct {
   double l_wing;       /* l_w, CG to wing mid-chord [m]                     */
   double l_elev;       /* l_e, elevator length [m]                          */
   double s_elev;       /* S_e, elevator area [m^2]                          */
+  double alpha_crit;   /* separation gate threshold on the wing AoA [rad]   */
+  int32_t gate;        /* 1: shed both edges only while alpha_w > alpha_crit,
+                          the trailing edge alone otherwise (shed_mode BOTH) */
+  int32_t pad_;
 } orc_params;
+
+/* Wing angle of attack (the separation criterion of Sec. III-A, measured
+ * like the elevator's angle of Sec. III-B): pitch minus the direction of the
+ * wing point's velocity, alpha_w = theta - atan2(zd_w, xd_w). */
+double orc_wing_aoa(const orc_params *p, const double *g);
 
 /* Kernels (Sec. III-A, Eqs. 4 and 5), per unit circulation. */
 void orc_kernel_sing(double dx, double dz, double *kx, double *kz);

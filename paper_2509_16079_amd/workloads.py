@@ -39,10 +39,11 @@ def f32(a):
 
 
 def make_params(n_bound, *, chord=0.3, r_core=0.01, decay=0.1, n_wake_max=0,
-                shed_mode=SHED_BOTH, prescribed=0, **over):
+                shed_mode=SHED_BOTH, prescribed=0, gate=0, alpha_crit=0.0, **over):
     p = dict(n_bound=int(n_bound), n_wake_max=int(n_wake_max), shed_mode=int(shed_mode),
              prescribed=int(prescribed), chord=float(chord), shed_frac=0.02,
-             r_core=float(r_core), decay=float(decay))
+             r_core=float(r_core), decay=float(decay), gate=int(gate),
+             alpha_crit=float(alpha_crit))
     p.update(GLIDER)
     p.update(over)
     for k, v in list(p.items()):

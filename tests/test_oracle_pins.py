@@ -503,3 +503,66 @@ def test_p16_bernoulli_lift_agrees_with_vortex_impulse_theorem(mode):
     else:
         # both edges shed: same sign and magnitude within a factor of two
         assert 0.5 < f_bern[1] / f_imp[1] < 2.0
+
+
+# --------------------------------------- P17 separation gate (reading R12)
+
+def _gated(g0, steps, alpha_crit, dt=0.005, nb=16, gate=1, mode=W.SHED_BOTH, prescribed=1):
+    p = base_params(nb, decay=0.0, n_wake_max=0, shed_mode=mode, prescribed=prescribed,
+                    gate=gate, alpha_crit=alpha_crit)
+    return O.rollout_batch(p, 1, steps, dt, np.array([g0]), np.zeros((1, nb)),
+                           np.array([0, 0], dtype=np.int64), None, np.zeros(0), np.zeros(0),
+                           np.zeros(0), None, np.zeros((1, steps)), W.X_GOAL, W.Q_POS_PITCH,
+                           traj=True, final_wake=True)
+
+
+@pytest.mark.parametrize("alpha_deg,crit_deg,per_step", [(5, 4, 2), (5, 6, 1)])
+def test_p17_level_flight_gate_compares_pitch_with_the_threshold(alpha_deg, crit_deg, per_step):
+    # level flight at 6 m/s, no rotation: the wing's angle of attack is the
+    # pitch itself, so the leading edge sheds every step or never
+    a = math.radians(alpha_deg)
+    out = _gated([0, 0, a, 0, 6.0, 0, 0], 30, math.radians(crit_deg))
+    assert out["n_final"][0] == per_step * 30
+
+
+@pytest.mark.parametrize("crit_deg,per_step", [(4.7, 2), (4.8, 1)])
+def test_p17_sinking_plate_sees_incidence_atan_w_over_u(crit_deg, per_step):
+    # a level plate sinking at 0.5 m/s while flying at 6 m/s meets the air at
+    # atan(0.5 / 6) = 4.764 degrees
+    out = _gated([0, 0, 0, 0, 6.0, -0.5, 0], 20, math.radians(crit_deg))
+    assert out["n_final"][0] == per_step * 20
+
+
+def test_p17_pitching_plate_sheds_from_the_leading_edge_while_past_critical():
+    # prescribed pitch-up at 2 rad/s from -5 degrees: theta_n = theta_0 + n dt q
+    # exactly; the wing point moves at (U + l_w q sin theta, -l_w q cos theta)
+    U, q, dt, steps, crit = 6.0, 2.0, 0.005, 80, math.radians(3.0)
+    th0 = math.radians(-5.0)
+    out = _gated([0, 0, th0, 0, U, 0, q], steps, crit, dt=dt)
+    lw = W.GLIDER["l_wing"]
+    th = th0 + dt * q * np.arange(steps)
+    aoa = th - np.arctan2(-lw * q * np.cos(th), U + lw * q * np.sin(th))
+    assert np.min(np.abs(aoa - crit)) > 1e-6          # no step sits on the threshold
+    assert 0 < np.sum(aoa > crit) < steps
+    assert out["n_final"][0] == steps + int(np.sum(aoa > crit))
+    assert np.allclose(out["traj"][0, :steps, 2], th, rtol=0, atol=1e-14)
+
+
+def test_p17_gate_always_open_or_closed_reduces_to_the_fixed_modes():
+    wl = W.realtime(K=2, H=40)
+    def run(**kw):
+        p = dict(wl.params, **kw)
+        return O.rollout_batch(p, wl.K, wl.H, wl.dt, wl.g0, wl.gb0, wl.field_off, wl.field_of,
+                               wl.wx, wl.wz, wl.wg, wl.pairs, wl.u, wl.x_goal, wl.q_diag,
+                               traj=True, final_wake=True)
+    def wake(o, k):
+        a, n = int(o["out_off"][k]), int(o["n_final"][k])
+        return np.concatenate([o["wx"][a:a + n], o["wz"][a:a + n], o["wg"][a:a + n]])
+    both, te = run(), run(shed_mode=W.SHED_TE)
+    opened, closed = run(gate=1, alpha_crit=-10.0), run(gate=1, alpha_crit=10.0)
+    for got, want in ((opened, both), (closed, te)):
+        assert np.array_equal(got["traj"], want["traj"])
+        assert np.array_equal(got["n_final"], want["n_final"])
+        for k in range(wl.K):
+            assert np.array_equal(wake(got, k), wake(want, k))
+    assert te["n_final"][0] == wl.n0[0] + wl.H and both["n_final"][0] == wl.n0[0] + 2 * wl.H
