@@ -68,7 +68,7 @@ extern "C" {
 typedef struct {
   int32_t n_bound;    /* N_b bound vortices on the chord, 1..64            */
   int32_t n_wake_max; /* N_w,max: merge the two oldest above it; <= 0: off */
-  int32_t shed_mode;  /* VPM_SHED_*; vpm_rollout_batch takes BOTH only     */
+  int32_t shed_mode;  /* VPM_SHED_*: both edges, trailing edge only, none  */
   int32_t precision;  /* VPM_FP32C or VPM_FP64                             */
   double chord;       /* c [m]                                             */
   double shed_frac;   /* delta_s / c; the paper uses 0.02                  */
@@ -83,6 +83,13 @@ typedef struct {
   double l_wing;      /* l_w: CG to wing mid-chord [m]                     */
   double l_elev;      /* l_e: elevator length [m]                          */
   double s_elev;      /* S_e: elevator area [m^2]                          */
+  double alpha_crit;  /* separation threshold on the wing AoA [rad]        */
+  int32_t gate;       /* 1 (needs shed_mode BOTH): a step sheds from both
+                         edges while the wing's angle of attack, pitch minus
+                         the direction of the wing point's velocity, exceeds
+                         alpha_crit, from the trailing edge only otherwise
+                         (Sec. III-A); 0: shed_mode every step              */
+  int32_t reserved;   /* 0                                                 */
 } vpm_params;
 
 /* One batch of K independent rollouts of H explicit-Euler steps of the
@@ -126,8 +133,11 @@ typedef struct {
   double *cost;           /* [K] J of Eq. 24; +inf when non-finite          */
   int32_t *status;        /* [K] VPM_ROLLOUT_* bits                         */
   double *traj;           /* [K][H+1][7] states, or NULL                    */
-  double *gamma_s;        /* [K][H][N_b+2] surface circulations per step
-                             (bound, LEV, TEV), or NULL                     */
+  double *gamma_s;        /* [K][H][S] surface circulations per step, or
+                             NULL; S = N_b + 2 (bound, LEV, TEV), N_b + 1
+                             (bound, TEV) or N_b by shed_mode; a gated step
+                             that sheds from the trailing edge only writes
+                             (bound, TEV) and a zero                        */
   int64_t *pair_count;    /* [K] pair-interactions the rollout's steps
                              comprise (method count), or NULL               */
   const int64_t *wake_off; /* [K+1] output capacity layout, or NULL         */
@@ -193,9 +203,14 @@ VPM_API int vpm_validate_batch(const vpm_params *params, const vpm_batch_in *in,
  * (Eq. 16) over the wake and the bound vortices, explicit Euler advection
  * and decay (Eq. 17), merging of the two oldest vortices above N_w,max, the
  * disturbance termination test (Sec. V) and the explicit Euler glider step.
- * Errors: VPM_EINVAL (bad sizes, NULL required pointers, shed_mode other
- * than BOTH; or, during stream capture, a first call that would have to
- * build a plate inverse or grow a context buffer), VPM_ECAPACITY
+ * Each step sheds per shed_mode, or with the separation gate on per the
+ * wing's angle of attack at the start of the step (decided in FP64 from the
+ * stored state in both precisions); an edge that does not shed drops its
+ * unknown and its collocation row from the system. The wake capacity rule
+ * (N_0 + 2H) is the same for every mode.
+ * Errors: VPM_EINVAL (bad sizes, NULL required pointers, invalid params; or,
+ * during stream capture, a first call that would have to build a plate
+ * inverse or grow a context buffer), VPM_ECAPACITY
  * (max_wake0 + 2H beyond the LDS limit when VPM_PATH_LDS is forced),
  * VPM_ENOMEM, VPM_ESINGULAR, VPM_EDEVICE.
  * Graph capture: the call may be captured into a HIP graph once an eager
@@ -323,7 +338,9 @@ VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0,
 
 /* Exact pair-interaction count of one rollout (host arithmetic): per step
  * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b
- * bound pairs with N_w' = N_w + 2, merging above n_wake_max (> 0). */
+ * bound pairs with N_w' = N_w + 2 (both edges shed), merging above
+ * n_wake_max (> 0). The pair_count output of vpm_rollout_batch counts the
+ * vortices each step actually sheds. */
 VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,
                                int32_t n_wake_max);
 

@@ -99,6 +99,8 @@ def lib(f32_state: bool = False):
         L.orc_cost.argtypes = [P, P, P]
         L.orc_cost.restype = d
         L.orc_mppi.argtypes = [i32, i32, P, d, P, P, P, P, P, P]
+        L.orc_wing_aoa.argtypes = [P, P]
+        L.orc_wing_aoa.restype = d
         _libs[path] = L
     return _libs[path]
 
@@ -161,6 +163,16 @@ def plate_geometry(params: dict, g):
     lib().orc_plate_geometry(C.byref(p), _p(g), *[_p(out[k]) for k in
                              ("x_w", "xw_dot", "rc", "rb", "r_lev", "r_tev", "n_hat", "t_hat")])
     return out
+
+
+def wing_aoa(params: dict, g) -> np.ndarray:
+    """Sec. III-A: the wing's angle of attack (pitch minus the direction of
+    the wing point's velocity) in each state of g [..., 7]."""
+    p = make_params(params)
+    g = _f64(g)
+    flat = g.reshape(-1, 7)
+    out = np.array([lib().orc_wing_aoa(C.byref(p), _p(np.ascontiguousarray(r))) for r in flat])
+    return out.reshape(g.shape[:-1])
 
 
 def system_size(n_bound, shed_mode=SHED_BOTH):

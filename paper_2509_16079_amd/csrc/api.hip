@@ -41,6 +41,11 @@ int check_params(const vpm_params *p) {
                       p->l_elev, p->s_elev};
   for (double v : f)
     if (!std::isfinite(v)) return fail(VPM_EINVAL, "non-finite parameter");
+  if (p->gate != 0 && p->gate != 1) return fail(VPM_EINVAL, "gate must be 0 or 1");
+  if (p->gate && (p->shed_mode != VPM_SHED_BOTH || !std::isfinite(p->alpha_crit)))
+    return fail(VPM_EINVAL, "the separation gate needs shed_mode BOTH and a finite alpha_crit");
+  if (p->shed_mode == VPM_SHED_NONE && p->n_bound < 2)
+    return fail(VPM_EINVAL, "shed_mode NONE needs n_bound >= 2");
   return VPM_OK;
 }
 
@@ -63,8 +68,6 @@ VPM_API int vpm_validate_batch(const vpm_params *p, const vpm_batch_in *in,
                                const vpm_batch_out *out) {
   int rc = vpm::check_params(p);
   if (rc != VPM_OK) return rc;
-  if (p->shed_mode != VPM_SHED_BOTH)
-    return fail(VPM_EINVAL, "vpm_rollout_batch supports shed_mode BOTH only");
   if (!in || !out) return fail(VPM_EINVAL, "in or out is NULL");
   if (in->K < 1 || in->H < 1) return fail(VPM_EINVAL, "K and H must be >= 1");
   if (!vpm::finite_pos(in->dt)) return fail(VPM_EINVAL, "dt must be > 0");
@@ -159,11 +162,13 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
   int rc = vpm_validate_batch(params, in, out);
   if (rc != VPM_OK) return rc;
   VPM_HIP_TRY(hipSetDevice(ctx->device));
-  const double *kinv = nullptr;
-  rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_BOTH, &kinv,
-                                 vpm::stream_capturing(static_cast<hipStream_t>(stream)));
+  const bool capturing = vpm::stream_capturing(static_cast<hipStream_t>(stream));
+  const double *kinv = nullptr, *kinv_te = nullptr;
+  rc = vpm::plate_inverse_device(ctx, params, params->shed_mode, &kinv, capturing);
+  if (rc == VPM_OK && params->gate)
+    rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_TE, &kinv_te, capturing);
   if (rc != VPM_OK) return rc;
-  return vpm::launch_rollout(ctx, params, in, out, kinv,
+  return vpm::launch_rollout(ctx, params, in, out, kinv, kinv_te,
                              static_cast<hipStream_t>(stream));
 }
 
@@ -200,7 +205,9 @@ VPM_API int vpm_reserve(vpm_ctx *ctx, const vpm_params *params, int32_t K, int32
     return fail(VPM_EINVAL, "K, H, n_fields must be >= 1 and max_wake0 >= 0");
   VPM_HIP_TRY(hipSetDevice(ctx->device));
   const double *kinv = nullptr;
-  rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_BOTH, &kinv, false);
+  rc = vpm::plate_inverse_device(ctx, params, params->shed_mode, &kinv, false);
+  if (rc == VPM_OK && params->gate)
+    rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_TE, &kinv, false);
   if (rc != VPM_OK) return rc;
   return vpm::reserve_rollout(ctx, params, K, H, max_wake0, n_fields);
 }

@@ -58,11 +58,14 @@ template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
 // Kernel argument block, filled on the host.
 struct KArgs {
   int K, H, nb, S, n_wake_max, max_wake0, n_pairs, cap, n_fields;
+  int mode, gate, n_inv;  // shedding mode, separation gate, inverse entries staged
+  double alpha_crit;
   double dt, chord, shed_frac, r_core, decay, rho, span, grav, mass, inertia;
   double inv_dt, inv_lb, inv_mass, inv_inertia;  // host reciprocals
   double l_body, l_wing, l_elev, s_elev;
   double x_goal[7], q_diag[7];
   const double *g0, *gb0, *wx, *wz, *wg, *u_mean, *u_eps, *kinv_t;
+  const double *kinv_te;  // trailing-edge-only inverse (gate on), after kinv_t in LDS
   const int64_t *field_off;
   const int32_t *field_of, *pairs;
   double *g_final, *cost, *traj, *gamma_s, *wx_out, *wz_out, *wg_out;
@@ -87,6 +90,7 @@ template <typename R> struct Shared {
   int head, n_w, status;
   int claimed;  // rollout claimed from the work queue
   int slot;     // issue-priority slot of this workgroup (see rotate_priority)
+  int mode_step, n_shed;  // this step's shedding mode and vortices shed
   int pa[kMaxPairs], pb[kMaxPairs];
   long long pairs;
 };
@@ -290,6 +294,19 @@ template <typename R>
 __device__ void prologue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src) {
   geometry(a, sh);
+  // Sec. III-A separation gate: the leading edge sheds only while the wing's
+  // angle of attack (pitch minus the direction of the wing point's velocity)
+  // exceeds the critical angle; decided in FP64 from the stored state
+  int mode = a.mode;
+  if (a.gate) {
+    const double th = sh.g[2], thd = sh.g[6];
+    const double xdw = double(sh.g[4]) + a.l_wing * thd * sin(th);
+    const double zdw = double(sh.g[5]) - a.l_wing * thd * cos(th);
+    const double aoa = th - atan2(zdw, xdw);
+    mode = aoa > a.alpha_crit ? VPM_SHED_BOTH : VPM_SHED_TE;
+  }
+  sh.mode_step = mode;
+  sh.n_shed = mode == VPM_SHED_BOTH ? 2 : mode == VPM_SHED_TE ? 1 : 0;
   for (int q = 0; q < kMaxPairs; ++q) {
     const int pa = sh.pa[q], pb = sh.pb[q];
     if (pa < 0) continue;
@@ -357,7 +374,13 @@ __device__ __forceinline__ void solve_section(
     const double2 *vsurf, const double *kinv, int k, int n, int head, int n_w,
     int lane, double u_n) {
   using Src = typename SrcOf<R>::type;
-  const int nb = a.nb, S = a.S, nc = nb + 1;
+  const int nb = a.nb, nc = nb + 1;
+  // this step's system (Sec. III-A): BOTH has N_b + 2 unknowns, TE-only
+  // drops the LEV column and the LE row, NONE both edges' (the Kelvin row
+  // is always last)
+  const int mode = __builtin_amdgcn_readfirstlane(sh.mode_step);
+  const int S = system_size(nb, mode), c0 = first_row(mode);
+  if (a.gate && mode == VPM_SHED_TE) kinv += a.S * a.S;
   const double dt = a.dt, lb = a.chord / nb;
   const R dtr = R(dt);
   double sg = 0.0;
@@ -371,8 +394,9 @@ __device__ __forceinline__ void solve_section(
   auto rhs = [&](int r) -> double {
     if (r >= S) return 0.0;
     if (r == S - 1) return -sum_gw;
-    const double px = lex + r * lb * etx, pz = lez + r * lb * etz;
-    const double2 vw = vsurf[r];
+    const int c = r + c0;  // collocation point of row r
+    const double px = lex + c * lb * etx, pz = lez + c * lb * etz;
+    const double2 vw = vsurf[c];
     const double vx = vw.x - xwdx + thd * (pz - xwz);
     const double vz = vw.y - xwdz - thd * (px - xwx);
     return -(vx * enx + vz * enz);
@@ -406,11 +430,13 @@ __device__ __forceinline__ void solve_section(
     }
   }
   auto row = [&](int r) -> double { return r < 64 ? bcast(gam0, r) : bcast(gam1, r - 64); };
-  const double glev = row(nb), gtev = row(nb + 1);
-  if (a.gamma_s) {
-    double *gs = a.gamma_s + ((size_t)k * a.H + n) * S;
-    if (lane < S) gs[lane] = gam0;
-    if (lane + 64 < S) gs[lane + 64] = gam1;
+  const double r_nb = row(nb), r_nb1 = row(nb + 1);  // both read unconditionally
+  const double glev = mode == VPM_SHED_BOTH ? r_nb : 0.0;
+  const double gtev = mode == VPM_SHED_BOTH ? r_nb1 : mode == VPM_SHED_TE ? r_nb : 0.0;
+  if (a.gamma_s) {  // a.S entries per step; a smaller system pads with zeros
+    double *gs = a.gamma_s + ((size_t)k * a.H + n) * a.S;
+    if (lane < a.S) gs[lane] = lane < S ? gam0 : 0.0;
+    if (lane + 64 < a.S) gs[lane + 64] = lane + 64 < S ? gam1 : 0.0;
   }
   // Eqs. 13-15. With P_j the prefix sums of Gamma_b, the force needs
   // sum_j (P_j - P'_j) = sum_k (N_b - k) dGamma_k and the moment
@@ -466,15 +492,22 @@ __device__ __forceinline__ void solve_section(
     sh.gn[4] = xd + dtr * ax_;
     sh.gn[5] = zd + dtr * az_;
     sh.gn[6] = thr + dtr * ath;
-    // shedding: LEV then TEV join the wake tail (Sec. III-A)
-    const int p = head + n_w;
+    // shedding (Sec. III-A): the LEV, if this step sheds one, then the TEV
+    // join the wake tail; an edge that does not shed contributes zero
+    // strength to pass B and nothing to the wake
+    int p = head + n_w;
     sh.shed_g[0] = R(glev * kInv2Pi);
     sh.shed_g[1] = R(gtev * kInv2Pi);
-    src[p] = Src{sh.lev[0], sh.lev[1], sh.shed_g[0], R(0)};
-    src[p + 1] = Src{sh.tev[0], sh.tev[1], sh.shed_g[1], R(0)};
     const double2 vl = vsurf[2 * nb + 1], vt = vsurf[2 * nb + 2];
-    vel[p] = Vec2<R>{R(vl.x), R(vl.y)};
-    vel[p + 1] = Vec2<R>{R(vt.x), R(vt.y)};
+    if (mode == VPM_SHED_BOTH) {
+      src[p] = Src{sh.lev[0], sh.lev[1], sh.shed_g[0], R(0)};
+      vel[p] = Vec2<R>{R(vl.x), R(vl.y)};
+      ++p;
+    }
+    if (mode != VPM_SHED_NONE) {
+      src[p] = Src{sh.tev[0], sh.tev[1], sh.shed_g[1], R(0)};
+      vel[p] = Vec2<R>{R(vt.x), R(vt.y)};
+    }
   }
 }
 
@@ -579,7 +612,7 @@ template <typename R>
 __device__ void epilogue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src, int k, int n, int n_w) {
   using Src = typename SrcOf<R>::type;
-  const int nb = a.nb, m = n_w + 2;
+  const int nb = a.nb, m = n_w + sh.n_shed;
   const bool last = (n == a.H - 1);
   sh.pairs += (long long)n_w * (2 * nb + 1) + (long long)m * (m - 1) + (long long)m * nb;
   int h = sh.head, cnt = m;
@@ -726,6 +759,14 @@ __device__ inline int simd_id() {
   return static_cast<int>((__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11)) >> 4) & 3u);
 }
 
+// Copy the plate inverse into LDS: the shedding mode's S x S system, then
+// (separation gate on) the trailing-edge-only system right after it.
+__device__ inline void stage_inverses(const KArgs &a, double *kinv, int tid, int nthr) {
+  const int n_main = a.S * a.S;
+  for (int q = tid; q < a.n_inv; q += nthr)
+    kinv[q] = q < n_main ? a.kinv_t[q] : a.kinv_te[q - n_main];
+}
+
 // LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
@@ -746,7 +787,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
   // it are counted in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_surf = 2 * a.nb + 3;
-  for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
+  stage_inverses(a, kinv, tid, kThr);
   if (tid == 0) sh.slot = simd_id();
   int fallback = blockIdx.x;
   for (;;) {
@@ -762,7 +803,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         __syncthreads();
       }
       rotate_priority(sh.slot, n);
-      const int head = sh.head, n_w = sh.n_w;
+      const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
       const int NT = n_surf + n_w;
       // this step's control, loaded now so its latency hides behind pass A
       double u_m = 0.0, u_e = 0.0;
@@ -813,7 +854,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       if (wave == 0)
         solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e);
       __syncthreads();
-      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr,
+      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
       if (tid == 0) epilogue(a, sh, src, k, n, n_w);
@@ -879,7 +920,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
   // it are counted in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_surf = 2 * a.nb + 3;
-  for (int q = tid; q < a.S * a.S; q += kThr) kinv[q] = a.kinv_t[q];
+  stage_inverses(a, kinv, tid, kThr);
 
   int next_static = blockIdx.x;
   for (;;) {
@@ -899,7 +940,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
         if (tid == 0) prologue(a, sh, src);
         __syncthreads();
       }
-      const int head = sh.head, n_w = sh.n_w;
+      const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
       const int NT = n_surf + n_w;
       double u_m = 0.0, u_e = 0.0;  // this step's control, loaded before pass A
       if (tid == 0) {
@@ -922,7 +963,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       if (wave == 0)
         solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e);
       __syncthreads();
-      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + 2, tid, kThr,
+      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
       if (tid == 0) epilogue(a, sh, src, k, n, n_w);
@@ -984,9 +1025,18 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
 
 // ------------------------------------------------------------------ host
 
+// Doubles of plate inverse staged in LDS: the system of the shedding mode,
+// and with the separation gate also the trailing-edge-only system.
+int inverse_entries(const vpm_params *p) {
+  const int s = system_size(p->n_bound, p->shed_mode);
+  const int s_te = system_size(p->n_bound, VPM_SHED_TE);
+  return s * s + (p->gate ? s_te * s_te : 0);
+}
+
+// n_inv: doubles of the staged inverse(s)
 template <typename R>
-size_t lds_fixed_bytes(int nb, int S, int nw, int tmax) {
-  return (size_t)S * S * sizeof(double) + (size_t)(2 * nb + 3) * sizeof(double2) +
+size_t lds_fixed_bytes(int nb, int n_inv, int nw, int tmax) {
+  return (size_t)n_inv * sizeof(double) + (size_t)(2 * nb + 3) * sizeof(double2) +
          (size_t)nw * 64 * tmax * sizeof(Vec2<R>) + 32 + sizeof(Shared<R>);
 }
 template <typename R> constexpr size_t lds_per_vortex() {
@@ -999,7 +1049,7 @@ int lds_layout(int cap, int nb, int nw, int tmax, KArgs &a) {
   off += (size_t)cap * sizeof(typename SrcOf<R>::type);
   off = (off + 15) & ~size_t(15);
   a.off_kinv = static_cast<int>(off);
-  off += (size_t)a.S * a.S * sizeof(double);
+  off += (size_t)a.n_inv * sizeof(double);
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = static_cast<int>(off);
@@ -1013,7 +1063,7 @@ template <typename R>
 int stream_layout(int nb, KArgs &a) {
   size_t off = (size_t)kStreamTile * sizeof(typename SrcOf<R>::type);
   a.off_kinv = static_cast<int>(off);
-  off += (size_t)a.S * a.S * sizeof(double);
+  off += (size_t)a.n_inv * sizeof(double);
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = a.off_vel = 0;
@@ -1092,8 +1142,8 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
 
 // Largest capacity a workgroup of the LDS kernel can hold within `bytes`.
 template <typename R>
-int lds_capacity(int nb, int S, int nw, int tmax, size_t bytes) {
-  const size_t fixed = lds_fixed_bytes<R>(nb, S, nw, tmax);
+int lds_capacity(int nb, int n_inv, int nw, int tmax, size_t bytes) {
+  const size_t fixed = lds_fixed_bytes<R>(nb, n_inv, nw, tmax);
   return bytes > fixed ? static_cast<int>((bytes - fixed) / lds_per_vortex<R>()) : 0;
 }
 
@@ -1165,8 +1215,8 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
   const int cap = a.cap;  // max_wake0 + 2H
   const Tune t_s = class_tune<R>(ctx, VPM_CLASS_SMALL), t_l = class_tune<R>(ctx, VPM_CLASS_LARGE);
   const Tune t_x = class_tune<R>(ctx, VPM_CLASS_STREAM);
-  const int cap_small = lds_capacity<R>(a.nb, a.S, kNwSmall, t_s.tmax, ctx->max_lds / 4);
-  const int cap_large = lds_capacity<R>(a.nb, a.S, kNwLarge, t_l.tmax, ctx->max_lds);
+  const int cap_small = lds_capacity<R>(a.nb, a.n_inv, kNwSmall, t_s.tmax, ctx->max_lds / 4);
+  const int cap_large = lds_capacity<R>(a.nb, a.n_inv, kNwLarge, t_l.tmax, ctx->max_lds);
   const Queue none{nullptr, nullptr, nullptr, 0};
   const bool stream_only = path == VPM_PATH_STREAM;
   if (a.n_fields == 1 || path == VPM_PATH_LDS || stream_only) {
@@ -1254,10 +1304,10 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 // Grow the context buffers that a batch of these sizes would need (the same
 // class decisions as run_batch), outside any stream capture.
 template <typename R>
-int reserve_batch(vpm_ctx *ctx, int nb, int K, int cap, int n_fields) {
+int reserve_batch(vpm_ctx *ctx, int nb, int n_inv, int K, int cap, int n_fields) {
   constexpr int kNwLarge = sizeof(R) == 4 ? 16 : 8;
   const int cap_large =
-      lds_capacity<R>(nb, nb + 2, kNwLarge, class_tune<R>(ctx, VPM_CLASS_LARGE).tmax, ctx->max_lds);
+      lds_capacity<R>(nb, n_inv, kNwLarge, class_tune<R>(ctx, VPM_CLASS_LARGE).tmax, ctx->max_lds);
   const int path = ctx->path;
   std::lock_guard<std::mutex> lock(ctx->ws_mu);
   if (path == VPM_PATH_STREAM || (path == VPM_PATH_AUTO && cap > cap_large)) {
@@ -1278,22 +1328,28 @@ int reserve_batch(vpm_ctx *ctx, int nb, int K, int cap, int n_fields) {
 int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wake0,
                     int n_fields) {
   const int cap = max_wake0 + 2 * H;
-  if (p->precision == VPM_FP64) return reserve_batch<double>(ctx, p->n_bound, K, cap, n_fields);
-  return reserve_batch<float>(ctx, p->n_bound, K, cap, n_fields);
+  const int n_inv = inverse_entries(p);
+  if (p->precision == VPM_FP64)
+    return reserve_batch<double>(ctx, p->n_bound, n_inv, K, cap, n_fields);
+  return reserve_batch<float>(ctx, p->n_bound, n_inv, K, cap, n_fields);
 }
 
 int lds_resident_capacity(int nb) {
-  return lds_capacity<float>(nb, nb + 2, 16, 2, 163840);
+  return lds_capacity<float>(nb, (nb + 2) * (nb + 2), 16, 2, 163840);
 }
 
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
-                   vpm_batch_out *out, const double *kinv_t,
+                   vpm_batch_out *out, const double *kinv_t, const double *kinv_te,
                    hipStream_t stream) {
   KArgs a{};
   a.K = in->K;
   a.H = in->H;
   a.nb = p->n_bound;
-  a.S = system_size(p->n_bound, VPM_SHED_BOTH);
+  a.S = system_size(p->n_bound, p->shed_mode);
+  a.mode = p->shed_mode;
+  a.gate = p->gate;
+  a.alpha_crit = p->alpha_crit;
+  a.n_inv = inverse_entries(p);
   a.n_wake_max = p->n_wake_max;
   a.max_wake0 = in->max_wake0;
   a.n_pairs = in->n_pairs;
@@ -1329,6 +1385,7 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.u_mean = in->u_mean;
   a.u_eps = in->u_eps;
   a.kinv_t = kinv_t;
+  a.kinv_te = p->gate ? kinv_te : nullptr;
   a.field_off = in->field_off;
   a.field_of = in->field_of;
   a.pairs = in->n_pairs > 0 ? in->pairs : nullptr;

@@ -30,11 +30,11 @@ constexpr int kMaxPairs = 4;
 constexpr int kMaxBound = 64;
 
 // System size per shedding mode (bound unknowns, then LEV, then TEV).
-inline int system_size(int nb, int mode) {
+__host__ __device__ inline int system_size(int nb, int mode) {
   return mode == VPM_SHED_BOTH ? nb + 2 : mode == VPM_SHED_TE ? nb + 1 : nb;
 }
 // First collocation row of the system per mode (LE row dropped unless BOTH).
-inline int first_row(int mode) { return mode == VPM_SHED_BOTH ? 0 : 1; }
+__host__ __device__ inline int first_row(int mode) { return mode == VPM_SHED_BOTH ? 0 : 1; }
 
 // Host FP64: inverse of the surface matrix in the plate's body frame,
 // returned transposed (column j of the inverse is contiguous) so that lane
@@ -104,8 +104,10 @@ int lds_resident_capacity(int nb);
 int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wake0,
                     int n_fields);
 
+// kinv_t: inverse of the plate system of p->shed_mode; kinv_te: of the
+// trailing-edge-only system when the separation gate is on (else NULL).
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
-                   vpm_batch_out *out, const double *kinv_t,
+                   vpm_batch_out *out, const double *kinv_t, const double *kinv_te,
                    hipStream_t stream);
 int launch_plate_solve(const vpm_params *p, int B, const double *pose,
                        const double *vw_c, const double *sum_gw, int mode,

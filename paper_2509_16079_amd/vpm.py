@@ -19,6 +19,7 @@ OK, PENDING = 0, 1
 EINVAL, ENOMEM, EDEVICE, ESINGULAR, EBUDGET, ECAPACITY, ENOTFOUND = -1, -2, -3, -4, -5, -6, -7
 ROLLOUT_NONFINITE, ROLLOUT_CAPACITY, ROLLOUT_BADFIELD = 1, 2, 4
 SHED_BOTH, SHED_TE, SHED_NONE = 0, 1, 2
+_SHED_UNKNOWNS = {SHED_BOTH: 2, SHED_TE: 1, SHED_NONE: 0}  # edge unknowns per mode
 FP32C, FP64 = 0, 1
 PATH_AUTO, PATH_LDS, PATH_STREAM = 0, 1, 2
 CLASS_SMALL, CLASS_LARGE, CLASS_STREAM = 0, 1, 2
@@ -33,7 +34,8 @@ class Params(C.Structure):
     _fields_ = [("n_bound", _I), ("n_wake_max", _I), ("shed_mode", _I), ("precision", _I),
                 ("chord", _D), ("shed_frac", _D), ("r_core", _D), ("decay", _D), ("rho", _D),
                 ("span", _D), ("grav", _D), ("mass", _D), ("inertia", _D), ("l_body", _D),
-                ("l_wing", _D), ("l_elev", _D), ("s_elev", _D)]
+                ("l_wing", _D), ("l_elev", _D), ("s_elev", _D), ("alpha_crit", _D),
+                ("gate", _I), ("reserved", _I)]
 
 
 class BatchIn(C.Structure):
@@ -96,6 +98,8 @@ def make_params(d: dict, precision=FP32C) -> Params:
     for name, _ in Params._fields_:
         if name == "precision":
             p.precision = precision
+        elif name in ("gate", "alpha_crit", "reserved"):
+            setattr(p, name, d.get(name, 0))
         else:
             setattr(p, name, d[name])
     return p
@@ -171,7 +175,8 @@ class DeviceOutputs:
         self.cost = torch.empty(K, **f64)
         self.status = torch.empty(K, dtype=torch.int32, device=device)
         self.traj = torch.empty((K, H + 1, 7), **f64) if traj else None
-        self.gamma_s = torch.empty((K, H, nb + 2), **f64) if gamma_s else None
+        S = nb + _SHED_UNKNOWNS[db.wl.params.get("shed_mode", SHED_BOTH)]
+        self.gamma_s = torch.empty((K, H, S), **f64) if gamma_s else None
         self.pair_count = torch.empty(K, dtype=torch.int64, device=device) if pair_count else None
         self.wake_off = self.wx = self.wz = self.wg = self.n_final = None
         self.vel_last = self.n_vel_last = None
@@ -275,7 +280,7 @@ class Context:
         """FP64 surface solve for B poses (torch float64 CUDA tensors)."""
         import torch
         B = pose.shape[0]
-        S = params["n_bound"] + {SHED_BOTH: 2, SHED_TE: 1, SHED_NONE: 0}[shed_mode]
+        S = params["n_bound"] + _SHED_UNKNOWNS[shed_mode]
         gs = torch.empty((B, S), dtype=torch.float64, device=pose.device)
         p = make_params(params, FP64)
         check(lib().vpm_plate_solve(self.h, C.byref(p), B, _ptr(pose), _ptr(vw_c), _ptr(sum_gw),

@@ -15,7 +15,8 @@ os.environ.setdefault("EMU_N_CU", "4")
 
 from paper_2509_16079_amd import vpm as V  # noqa: E402
 from paper_2509_16079_amd import workloads as W  # noqa: E402
-from tests.parity import rel_l2, run_oracle, wake_segments  # noqa: E402
+from tests.parity import (gate_margin, gated_at_median, rel_l2, run_oracle,  # noqa: E402
+                          wake_segments, with_params)
 
 V.LIB_PATH = os.path.join(HERE, "_build", "libvpm_emu.so")
 
@@ -42,6 +43,12 @@ def cases():
         "large": lambda: W.uneven_batch(K=5, H=2, n_min=1100, n_max=7000),
         # the same with non-default kernel shapes in every class
         "large_tuned": lambda: W.uneven_batch(K=5, H=2, n_min=1100, n_max=7000),
+        # trailing-edge-only and no shedding (Sec. III-A modes)
+        "shed_te": lambda: with_params(W.realtime(K=2, H=6), shed_mode=W.SHED_TE),
+        "shed_none": lambda: with_params(W.uneven_batch(K=4, H=3, n_min=1, n_max=700),
+                                         shed_mode=W.SHED_NONE),
+        # separation gate switching between both-edge and trailing-edge steps
+        "gated": lambda: gated_at_median(W.realtime(K=4, H=8)),
     }
 
 
@@ -73,6 +80,7 @@ def main(names):
                 "g_final": rel_l2(g["g_final"], o["g_final"]),
                 "wake": wake,
                 "n_final_equal": bool(np.array_equal(g["n_final"], o["n_final"])),
+                "gate_margin": gate_margin(wl, o["traj"]) if wl.params.get("gate") else None,
                 "status": g["status"].tolist()}), flush=True)
     ctx.close()
 

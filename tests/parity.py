@@ -1,5 +1,7 @@
 """Helpers shared by the GPU parity tests: run one workload through the HIP
 library and through the CPU oracle on the same seeded inputs and compare."""
+from dataclasses import replace
+
 import numpy as np
 
 from oracle import oracle as O
@@ -35,3 +37,26 @@ def vel_segment(out, k):
 
 def describe(tag, **errs):
     return tag + " " + " ".join("%s=%.3e" % kv for kv in errs.items())
+
+
+def with_params(wl, **over):
+    """The workload with some plate/glider parameters replaced."""
+    p = dict(wl.params)
+    p.update(over)
+    return replace(wl, params=p, name=wl.name + "+" + ",".join(sorted(over)))
+
+
+def gated_at_median(wl):
+    """The workload with the separation gate on and the critical angle half
+    way between the two middle wing angles of attack of the ungated oracle
+    run, so that about half of the steps shed from the leading edge."""
+    o = run_oracle(wl, traj=True)
+    a = np.sort(O.wing_aoa(wl.params, o["traj"][:, :-1]).ravel())
+    i = a.size // 2
+    return with_params(wl, gate=1, alpha_crit=float(0.5 * (a[i - 1] + a[i])))
+
+
+def gate_margin(wl, traj):
+    """Smallest distance of a step's wing angle of attack from the critical
+    angle along the trajectories traj [K, H + 1, 7]."""
+    return float(np.min(np.abs(O.wing_aoa(wl.params, traj[:, :-1]) - wl.params["alpha_crit"])))

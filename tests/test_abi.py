@@ -67,12 +67,30 @@ def test_validation_rejects_bad_batch(field, value, code):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("n_bound", 0), ("n_bound", 65), ("shed_mode", 1), ("precision", 2), ("chord", 0.0),
+    ("n_bound", 0), ("n_bound", 65), ("shed_mode", 3), ("shed_mode", -1), ("gate", 2),
+    ("precision", 2), ("chord", 0.0),
     ("r_core", 0.0), ("mass", -1.0), ("inertia", 0.0), ("decay", -0.1), ("rho", float("inf")),
 ])
 def test_validation_rejects_bad_params(field, value):
     p, b, o = _valid_args()
     setattr(p, field, value)
+    assert _validate(p, b, o) == V.EINVAL
+
+
+def test_shedding_modes_and_gate_rules():
+    for mode in (V.SHED_BOTH, V.SHED_TE, V.SHED_NONE):
+        p, b, o = _valid_args()
+        p.shed_mode = mode
+        assert _validate(p, b, o) == V.OK
+    p, b, o = _valid_args()
+    p.gate, p.alpha_crit = 1, 0.1
+    assert _validate(p, b, o) == V.OK
+    for mode, crit in ((V.SHED_TE, 0.1), (V.SHED_NONE, 0.1), (V.SHED_BOTH, float("nan"))):
+        p, b, o = _valid_args()      # the gate switches between BOTH and TE only
+        p.gate, p.shed_mode, p.alpha_crit = 1, mode, crit
+        assert _validate(p, b, o) == V.EINVAL
+    p, b, o = _valid_args()
+    p.shed_mode, p.n_bound = V.SHED_NONE, 1  # no collocation row would remain
     assert _validate(p, b, o) == V.EINVAL
 
 

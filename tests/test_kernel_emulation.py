@@ -26,7 +26,8 @@ def emu_lib():
     return r.stdout.strip()
 
 
-@pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large", "large_tuned"])
+@pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large", "large_tuned",
+                                  "shed_te", "shed_none", "gated"])
 def test_emulated_kernels_match_oracle(emu_lib, case):
     try:
         r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), case],
@@ -40,6 +41,8 @@ def test_emulated_kernels_match_oracle(emu_lib, case):
         tol = TOL[row["prec"]]
         assert all(s == 0 for s in row["status"]), row
         assert row["n_final_equal"], row
+        if row["gate_margin"] is not None:  # the decisions are robust to rounding
+            assert row["gate_margin"] > 1e-5, row
         for key in ("traj", "gamma_s", "g_final"):
             assert row[key] <= tol, (key, row)
         assert row["wake"] <= 10 * tol, row
