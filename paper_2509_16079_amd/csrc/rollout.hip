@@ -290,21 +290,28 @@ __device__ void geometry(const KArgs &a, Shared<R> &sh) {
 }
 
 // Thread 0 at the start of a step: kinematics and termination.
-template <typename R>
+// Wing angle of attack of the separation gate (Sec. III-A): pitch minus the
+// direction of the wing point's velocity, in FP64. Out of line: inlined, its
+// sin/cos/atan2 raise the register pressure of the whole kernel, and the FP32
+// kernels spill.
+__device__ __noinline__ double wing_aoa(double th, double xd, double zd, double thd, double lw) {
+  const double xdw = xd + lw * thd * sin(th), zdw = zd - lw * thd * cos(th);
+  return th - atan2(zdw, xdw);
+}
+
+// GATE: the separation gate is on; only the gated kernel instances contain
+// the call (a call alone changes the register allocation of the kernel).
+template <typename R, bool GATE>
 __device__ void prologue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src) {
   geometry(a, sh);
-  // Sec. III-A separation gate: the leading edge sheds only while the wing's
-  // angle of attack (pitch minus the direction of the wing point's velocity)
-  // exceeds the critical angle; decided in FP64 from the stored state
   int mode = a.mode;
-  if (a.gate) {
-    const double th = sh.g[2], thd = sh.g[6];
-    const double xdw = double(sh.g[4]) + a.l_wing * thd * sin(th);
-    const double zdw = double(sh.g[5]) - a.l_wing * thd * cos(th);
-    const double aoa = th - atan2(zdw, xdw);
-    mode = aoa > a.alpha_crit ? VPM_SHED_BOTH : VPM_SHED_TE;
-  }
+  // Sec. III-A separation gate: the leading edge sheds only while the wing's
+  // angle of attack exceeds the critical angle; decided in FP64 from the
+  // stored state
+  if constexpr (GATE)
+    mode = wing_aoa(sh.g[2], sh.g[4], sh.g[5], sh.g[6], a.l_wing) > a.alpha_crit ? VPM_SHED_BOTH
+                                                                            : VPM_SHED_TE;
   sh.mode_step = mode;
   sh.n_shed = mode == VPM_SHED_BOTH ? 2 : mode == VPM_SHED_TE ? 1 : 0;
   for (int q = 0; q < kMaxPairs; ++q) {
@@ -608,7 +615,7 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
 
 // Thread 0 at the end of a step: merging and the glider step; then, unless
 // it is the last step, the next step's prologue.
-template <typename R>
+template <typename R, bool GATE>
 __device__ void epilogue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src, int k, int n, int n_w) {
   using Src = typename SrcOf<R>::type;
@@ -632,7 +639,7 @@ __device__ void epilogue(const KArgs &a, Shared<R> &sh,
     for (int i = 0; i < 7; ++i)
       a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
   if (last && a.n_vel_last) a.n_vel_last[k] = m;
-  if (!last) prologue(a, sh, src);
+  if (!last) prologue<R, GATE>(a, sh, src);
 }
 
 // Final outputs of rollout k.
@@ -770,7 +777,7 @@ __device__ inline void stage_inverses(const KArgs &a, double *kinv, int tid, int
 // LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
-template <typename R, int TMAX, int MINW, int NW, int TILE>
+template <typename R, int TMAX, int MINW, int NW, int TILE, bool GATE>
 __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
@@ -799,7 +806,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue(a, sh, src);
+        if (tid == 0) prologue<R, GATE>(a, sh, src);
         __syncthreads();
       }
       rotate_priority(sh.slot, n);
@@ -857,7 +864,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue(a, sh, src, k, n, n_w);
+      if (tid == 0) epilogue<R, GATE>(a, sh, src, k, n, n_w);
       __syncthreads();
     }
     finish(a, sh, src, k, tid, kThr);
@@ -903,7 +910,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
 // Persistent: each workgroup keeps its rollout's wake in workspace slot
 // blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
 // or, with a queue, claims them in planned order.
-template <typename R, int TMAX, int NW, int TILE>
+template <typename R, int TMAX, int NW, int TILE, bool GATE>
 __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
@@ -937,7 +944,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     __syncthreads();
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue(a, sh, src);
+        if (tid == 0) prologue<R, GATE>(a, sh, src);
         __syncthreads();
       }
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
@@ -966,7 +973,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue(a, sh, src, k, n, n_w);
+      if (tid == 0) epilogue<R, GATE>(a, sh, src, k, n, n_w);
       __syncthreads();
     }
     finish(a, sh, src, k, tid, kThr);
@@ -1089,7 +1096,8 @@ int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
                                    " does not fit the LDS-resident kernel");
-  auto kern = rollout_lds_kernel<R, TMAX, MINW, NW, TILE>;
+  auto kern = a.gate ? rollout_lds_kernel<R, TMAX, MINW, NW, TILE, true>
+                     : rollout_lds_kernel<R, TMAX, MINW, NW, TILE, false>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a, qu);
@@ -1126,7 +1134,8 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
   const int lds = stream_layout<R>(a.nb, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
-  auto kern = rollout_stream_kernel<R, TMAX, NW, TILE>;
+  auto kern = a.gate ? rollout_stream_kernel<R, TMAX, NW, TILE, true>
+                     : rollout_stream_kernel<R, TMAX, NW, TILE, false>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
