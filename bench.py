@@ -14,6 +14,11 @@ Workloads (``--workload``):
                       (log-uniform), FP32, planned persistent class kernels
   stress              K=8192, H=150, 16376-vortex Lamb-Oseen field, 64 bound
                       vortices, merging above 16384, FP32 (streamed wakes)
+  policy              the local feedback policy (Sec. IV-B) at the paper's
+                      controller size: least-squares Jacobians from K=256
+                      perturbed FP64 rollouts of 77 steps (dt = 10 ms) and
+                      the TVLQR recursion; one step = one vpm_policy call on
+                      resident trajectories
 The default run also replays the first requests of the serving trace through
 the replanning service (8 slots) and through the plain one-at-a-time path,
 reporting p50/p99 latency and rollouts/s for both. Prints one JSON line.
@@ -42,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress"],
+    ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress", "policy"],
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -347,6 +352,97 @@ def serving(n_requests, sweep=False):
     return out
 
 
+def policy_bytes(K, H):
+    """Algorithmic bytes of one vpm_policy call: trajectories, control
+    deviations and the nominal read once; A, B, gains, S and status written
+    once."""
+    return 8 * (K * (H + 1) * 7 + K * H + (H + 1) * 7) + 8 * H * (49 + 7 + 7) \
+        + 8 * (H + 1) * 49 + 4 * H
+
+
+def policy_main(args):
+    import torch
+
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    K, H = 256, 77
+    steps = 50 if args.steps is None else args.steps
+    warmup = 5 if args.warmup is None else args.warmup
+    wl = W.policy_batch(K=K, H=H)
+    ctx = V.Context(0)
+    db = V.DeviceBatch(wl)
+    out = V.DeviceOutputs(db, traj=True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.rollout(wl.params, db, out, V.FP64, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rollout_ms = e0.elapsed_time(e1)
+    traj, du = out.traj, db.u_eps[1:]
+    q_f = [400.0, 400.0, 10.0, 1.0, 1.0, 1.0, 1.0]   # TVLQR weights of Sec. V-A
+    q_c = [0.1, 0.1, 5.0, 0.1, 0.1, 0.1, 5.0]
+    r_c = 0.01
+    for _ in range(warmup):
+        pol = V.policy(ctx, traj[0], traj[1:], du, wl.dt, q_f, q_c, r_c, stream=stream)
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record(stream)
+        pol = V.policy(ctx, traj[0], traj[1:], du, wl.dt, q_f, q_c, r_c, stream=stream)
+        ev[1].record(stream)
+        evs.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    each = [a.elapsed_time(b) for a, b in evs]
+    kern = float(np.mean(each))
+    ms = 1e3 * wall / steps
+    nbytes = policy_bytes(K, H)
+    achieved = nbytes / (kern * 1e-3) / 1e9
+    line = {
+        "metric": "local feedback policy construction time (LS Jacobians + TVLQR)",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "policy: K=256 perturbed FP64 rollouts + nominal, H=77, "
+                               "dt=10 ms, N_b=32, one disturbance pair", "K": K, "H": H},
+        "policy_kernels_ms": kern,
+        "policy_kernels_ms_median": float(np.median(each)),
+        "rollout_batch_ms_fp64": rollout_ms,
+        "rank_deficient_steps": int(pol["status"].sum().item()),
+        "kernel_timing": "HIP events around each vpm_policy call (synthesis + Riccati) on its "
+                         "stream",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None},
+        "gpu_clock_after_timed_region": gpu_clock(),
+    }
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import policy as P
+        tr = traj.cpu().numpy()
+        dun = du.cpu().numpy()
+        reps = 0
+        with threadpool_limits(1):          # the oracle on one core
+            t0 = time.perf_counter()
+            while reps < 20 or time.perf_counter() - t0 < 2.0:
+                o = P.policy(tr[0], tr[1:], dun, wl.dt, q_f, q_c, r_c)
+                reps += 1
+            cpu_ms = 1e3 * (time.perf_counter() - t0) / reps
+        line["cpu_baseline"] = {"value": cpu_ms, "unit": "ms", "cores": 1, "kind": "oracle",
+                                "sample": "the whole workload (same trajectories), %d calls"
+                                          % reps}
+        g = {k: v.cpu().numpy() for k, v in pol.items() if v is not None}
+        line["error_vs_oracle"] = {
+            "gain_rel_l2": _rel_l2(g["gain"], o["gain"]),
+            "A_rel_l2": _rel_l2(g["a"], o["A"]), "S_rel_l2": _rel_l2(g["s"], o["S"]),
+            "status_equal": bool(np.array_equal(g["status"], o["status"]))}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -354,6 +450,8 @@ def main():
               "this build measures one GPU's share; see the sharding notes in DESIGN.md",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "policy":
+        return policy_main(args)
     import torch
 
     from paper_2509_16079_amd import vpm as V

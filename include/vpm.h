@@ -336,6 +336,52 @@ VPM_API int planner_poll(planner *p, uint64_t ticket, plan_result *res,
 VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0,
                                  int32_t n_bound, int32_t iterations);
 
+/* Local feedback policy from rollouts (Sec. IV-B). Least-squares Jacobians
+ * at every step (Eqs. 26-28): the rates of the K perturbed rollouts minus
+ * the nominal's, (x_{k+1} - x_k) / dt exactly for the explicit Euler step,
+ * regressed in FP64 on the state deviations of theta, phi, x_dot, z_dot,
+ * theta_dot and the control deviation; only the three acceleration rows are
+ * unknown (the 3 x 5 block A_hat and 3 x 1 block B_hat of Eq. 28), the
+ * kinematic rows are known (rates of x, z, theta are x_dot, z_dot,
+ * theta_dot; the rate of phi is u). The discrete system is the explicit
+ * Euler map A_k = I + dt dF/dx, B_k = dt dF/du. Then TVLQR (Eqs. 29-30):
+ * S_H = diag(q_f), S_k = A_k' S A_k - A_k' S B_k (r_c + B_k' S B_k)^-1
+ * B_k' S A_k + diag(q_c) with S = S_{k+1}, kept symmetric each step, and
+ * gain_k = (r_c + B_k' S B_k)^-1 B_k' S A_k; the policy is
+ * u_k = u_k^d - gain_k . (x_k - x_k^d). */
+typedef struct {
+  int32_t K;              /* perturbed rollouts (>= 1; fewer than 6 leave
+                             every step rank-deficient)                     */
+  int32_t H;              /* steps (>= 1)                                   */
+  double dt;              /* step of the rollouts (> 0)                     */
+  const double *traj_nom; /* device [H+1][7] nominal states                 */
+  const double *traj;     /* device [K][H+1][7] perturbed rollouts (the
+                             layout of vpm_batch_out.traj)                  */
+  const double *du;       /* device [K][H] control deviations u^i_k - u_k   */
+  double q_f[7];          /* host: diagonal of the final cost Q_f (>= 0)    */
+  double q_c[7];          /* host: diagonal of the running cost Q_c (>= 0)  */
+  double r_c;             /* host: control weight R_c (> 0)                 */
+} vpm_policy_in;
+
+typedef struct {
+  double *a;              /* device [H][7][7] A_k (row-major)               */
+  double *b;              /* device [H][7] B_k                              */
+  double *gain;           /* device [H][7] gain_k                           */
+  double *s;              /* device [H+1][7][7] S_k, or NULL                */
+  int32_t *status;        /* device [H]: 1 where the regression is rank-
+                             deficient (fewer than 6 samples, a zero
+                             column, or a Cholesky pivot of the column-
+                             scaled normal matrix <= 1e-14); that step
+                             takes A_hat = 0, B_hat = 0                     */
+} vpm_policy_out;
+
+/* Runs the synthesis (one workgroup per step) and the Riccati recursion
+ * (one wavefront) on `stream`; every buffer is caller-owned device memory,
+ * nothing is allocated. Errors: VPM_EINVAL (sizes, NULL required pointers,
+ * non-finite or negative weights, r_c <= 0), VPM_EDEVICE. */
+VPM_API int vpm_policy(vpm_ctx *ctx, const vpm_policy_in *in, vpm_policy_out *out,
+                       void *stream);
+
 /* Exact pair-interaction count of one rollout (host arithmetic): per step
  * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b
  * bound pairs with N_w' = N_w + 2 (both edges shed), merging above

@@ -26,7 +26,7 @@ u = phi_dot (Sec. III-B). Readings taken where the text is garbled:
   multiplies by A_k' ... A_k, which grows when the open loop is unstable.
 * A time step whose regression matrix [dX dU] (K x 6) is rank-deficient
   (fewer than 6 samples, a zero column, or a smallest singular value at most
-  1e-9 times the largest after scaling each column to unit norm) gets
+  1e-7 times the largest after scaling each column to unit norm) gets
   A_hat = 0, B_hat = 0 and a status flag.
 """
 from __future__ import annotations
@@ -36,7 +36,7 @@ import numpy as np
 N_X = 7
 ACC = (4, 5, 6)            # rows of the accelerations (A_hat, B_hat rows)
 REG = (2, 3, 4, 5, 6)      # state columns of A_hat
-RANK_TOL = 1e-9
+RANK_TOL = 1e-7
 
 
 def state_rates(traj: np.ndarray, dt: float) -> np.ndarray:

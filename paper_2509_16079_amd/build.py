@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvpm.so")
-SOURCES = ["api.hip", "plate_system.cpp", "rollout.hip", "solve_mppi.hip", "planner.hip"]
+SOURCES = ["api.hip", "plate_system.cpp", "rollout.hip", "solve_mppi.hip", "planner.hip",
+           "policy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -250,6 +250,25 @@ VPM_API int mppi_weights(vpm_ctx *ctx, int32_t K, int32_t H, const double *cost,
                           argmin, jmin, static_cast<hipStream_t>(stream));
 }
 
+VPM_API int vpm_policy(vpm_ctx *ctx, const vpm_policy_in *in, vpm_policy_out *out,
+                       void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  if (!in || !out) return fail(VPM_EINVAL, "in or out is NULL");
+  if (in->K < 1 || in->H < 1) return fail(VPM_EINVAL, "K and H must be >= 1");
+  if (!vpm::finite_pos(in->dt)) return fail(VPM_EINVAL, "dt must be > 0");
+  if (!vpm::finite_pos(in->r_c)) return fail(VPM_EINVAL, "r_c must be > 0");
+  for (int i = 0; i < 7; ++i)
+    if (!(std::isfinite(in->q_f[i]) && in->q_f[i] >= 0.0 && std::isfinite(in->q_c[i]) &&
+          in->q_c[i] >= 0.0))
+      return fail(VPM_EINVAL, "q_f and q_c must be finite and >= 0");
+  if (!in->traj_nom || !in->traj || !in->du)
+    return fail(VPM_EINVAL, "a required input pointer is NULL");
+  if (!out->a || !out->b || !out->gain || !out->status)
+    return fail(VPM_EINVAL, "a required output pointer is NULL");
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  return vpm::launch_policy(in, out, static_cast<hipStream_t>(stream));
+}
+
 VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,
                                int32_t n_wake_max) {
   int64_t total = 0, n = n0;

@@ -35,6 +35,7 @@
 #include <cmath>
 
 #include "vpm_internal.h"
+#include "wave_ops.h"
 
 namespace vpm {
 namespace {
@@ -94,35 +95,6 @@ template <typename R> struct Shared {
   int pa[kMaxPairs], pb[kMaxPairs];
   long long pairs;
 };
-
-// Value of v in lane j (uniform j) for every lane: two readlanes, no LDS.
-__device__ inline double bcast(double v, int j) {
-  const unsigned long long u = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(u), j);
-  const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(u >> 32), j);
-  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-
-// v from another lane of the same 16-lane row, by DPP control CTRL.
-template <int CTRL>
-__device__ inline double dpp(double v) {
-  const unsigned long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(static_cast<long long>(
-      (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo)));
-}
-
-// Sum of v over the 64 lanes (all active), in every lane, in a fixed order:
-// pairs, quads, then 8- and 16-lane rows by DPP (no LDS), then the four row
-// sums as (r0 + r1) + (r2 + r3).
-__device__ inline double wave_sum(double v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x124>(v);  // row_ror:4
-  v += dpp<0x128>(v);  // row_ror:8
-  return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
-}
 
 __device__ inline float rsq(float d) { return __builtin_amdgcn_rsqf(d); }
 __device__ inline double rsq(double d) { return 1.0 / sqrt(d); }

@@ -113,6 +113,7 @@ int launch_plate_solve(const vpm_params *p, int B, const double *pose,
                        const double *vw_c, const double *sum_gw, int mode,
                        const double *kinv_t, double *gamma_s,
                        hipStream_t stream);
+int launch_policy(const vpm_policy_in *in, vpm_policy_out *out, hipStream_t stream);
 int launch_mppi(int K, int H, const double *cost, double lambda,
                 const double *u_mean, const double *u_eps, double *w_out,
                 double *u_new, int32_t *argmin, double *jmin,

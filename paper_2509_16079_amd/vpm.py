@@ -74,10 +74,20 @@ def lib():
         L.vpm_reserve.argtypes = [_P, C.POINTER(Params), _I, _I, _I, _I]
         L.vpm_set_tuning.argtypes = [_P, _I, _I, _I]
         L.vpm_get_tuning.argtypes = [_P, _I, C.POINTER(_I), C.POINTER(_I)]
+        L.vpm_policy.argtypes = [_P, C.POINTER(PolicyIn), C.POINTER(PolicyOut), _P]
         L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
         L.vpm_pair_count.restype = C.c_int64
         _lib = L
     return _lib
+
+
+class PolicyIn(C.Structure):
+    _fields_ = [("K", _I), ("H", _I), ("dt", _D), ("traj_nom", _P), ("traj", _P), ("du", _P),
+                ("q_f", _D * 7), ("q_c", _D * 7), ("r_c", _D)]
+
+
+class PolicyOut(C.Structure):
+    _fields_ = [("a", _P), ("b", _P), ("gain", _P), ("s", _P), ("status", _P)]
 
 
 class VpmError(RuntimeError):
@@ -300,6 +310,36 @@ class Context:
                                  _ptr(w), _ptr(u_new), _ptr(am), _ptr(jm), _stream_handle(stream)),
               "mppi_weights")
         return w, u_new, am, jm
+
+
+def policy(ctx: Context, traj_nom, traj, du, dt, q_f, q_c, r_c, want_s=True, stream=None):
+    """Local feedback policy from rollouts (vpm_policy). traj_nom [H+1, 7],
+    traj [K, H+1, 7] and du [K, H] are float64 device tensors (traj may be
+    the rows of a larger [K', H+1, 7] batch). Returns a dict of device
+    tensors a [H, 7, 7], b [H, 7], gain [H, 7], s [H+1, 7, 7] (or None) and
+    status [H]."""
+    import torch
+    K, H1, _ = traj.shape
+    H = H1 - 1
+    for t, shape in ((traj_nom, (H1, 7)), (traj, (K, H1, 7)), (du, (K, H))):
+        if t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError("policy inputs must be contiguous float64 tensors of the stated shapes")
+    dev = traj.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = dict(a=torch.empty((H, 7, 7), **f64), b=torch.empty((H, 7), **f64),
+               gain=torch.empty((H, 7), **f64),
+               s=torch.empty((H + 1, 7, 7), **f64) if want_s else None,
+               status=torch.empty(H, dtype=torch.int32, device=dev))
+    pin = PolicyIn(K, H, float(dt), _ptr(traj_nom), _ptr(traj), _ptr(du))
+    for i in range(7):
+        pin.q_f[i] = float(q_f[i])
+        pin.q_c[i] = float(q_c[i])
+    pin.r_c = float(r_c)
+    pout = PolicyOut(_ptr(out["a"]), _ptr(out["b"]), _ptr(out["gain"]),
+                     _ptr(out["s"]) if want_s else None, _ptr(out["status"]))
+    check(lib().vpm_policy(ctx.h, C.byref(pin), C.byref(pout), _stream_handle(stream)),
+          "vpm_policy")
+    return out
 
 
 def run_workload(ctx: Context, wl, precision=FP32C, **want) -> dict:

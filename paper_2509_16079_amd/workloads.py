@@ -157,6 +157,42 @@ def realtime(seed=1, K=1024, H=200):
                     meta=dict(pair_gamma=float(gam), pair_x=float(xp), pair_zc=float(zc)))
 
 
+# Perturbation scales of the policy rollouts (the paper tunes its
+# covariances by sweeps and does not print them): positions 1 cm, angles
+# 0.01 rad, velocities 0.05 m/s, pitch rate 0.05 rad/s; controls 0.15.
+POLICY_SIGMA_X = np.array([0.01, 0.01, 0.01, 0.01, 0.05, 0.05, 0.05])
+POLICY_SIGMA_U = 0.15
+
+
+def policy_batch(seed=5, K=256, H=77, dt=0.01, n_bound=32):
+    """Rollouts for the local feedback policy (Sec. IV-B) at the size of the
+    paper's controller (MPPI batch 256, 77-step nominal, dt = 10 ms): rollout
+    0 is the nominal (7 m/s level start, elevator-rate sequence u_mean, no
+    perturbation); rollouts 1..K start from N(x_0, diag(POLICY_SIGMA_X)^2)
+    with controls u_mean + N(0, POLICY_SIGMA_U^2); one disturbance pair as in
+    the realtime batch. Returns a Workload of K + 1 rollouts."""
+    rng = _rng(seed)
+    p = make_params(n_bound, n_wake_max=800)
+    gam = rng.uniform(0.2, 0.8)
+    xp = rng.uniform(1.5, 2.5)
+    zc = rng.uniform(-0.3, 0.3)
+    x, z, g = _pair(xp, zc, gam)
+    wx, wz, wg = f32(x), f32(z), f32(g)
+    fo, fof, pairs = _one_field(K + 1, wx, wz, wg, [(0, 1)], H)
+    g0 = np.zeros((K + 1, 7))
+    g0[:, 4] = 7.0
+    g0[1:] += rng.normal(size=(K, 7)) * POLICY_SIGMA_X
+    eps = np.zeros((K + 1, H))
+    eps[1:] = rng.normal(0.0, POLICY_SIGMA_U, size=(K, H))
+    # elevator-rate sequence that pitches the glider up to about 40 degrees
+    # while it slows from 7 to about 4 m/s, a perch-like manoeuvre
+    u_mean = f32(-1.5 * np.sin(np.linspace(0.0, np.pi, H)))
+    return Workload("policy_K%d_H%d" % (K, H), p, K + 1, H, float(f32(dt)), f32(g0),
+                    np.zeros((K + 1, n_bound)), fo, fof, wx, wz, wg, pairs, u_mean, f32(eps),
+                    precision="fp64",
+                    meta=dict(pair_gamma=float(gam), pair_x=float(xp), pair_zc=float(zc)))
+
+
 def random_field(rng, n, box=(0.0, 3.0, -0.5, 0.5), sigma_gamma=0.05):
     """n vortices uniform in the box with N(0, sigma^2) strengths, shifted to
     zero total circulation (the paper's flow starts at zero circulation)."""

@@ -56,9 +56,40 @@ TUNINGS = {"large_tuned": [(V.CLASS_SMALL, 1, 256), (V.CLASS_LARGE, 4, 128),
                            (V.CLASS_STREAM, 2, 256)]}
 
 
+def policy_case(ctx, name):
+    """The policy kernels on linear data (known Jacobians) or on oracle VPM
+    rollouts, against the policy oracle."""
+    import torch
+    from oracle import policy as P
+    from tests.policy_data import euler_linear_data
+    if name == "policy_linear":
+        rng = np.random.default_rng(3)
+        K, H, dt = 40, 6, 0.01
+        nom, traj, du = euler_linear_data(rng, K, H, dt, rng.normal(size=(H, 3, 5)),
+                                          rng.normal(size=(H, 3)))
+        du[:, 2] = 0.0                              # one rank-deficient step
+    else:
+        wl = W.policy_batch(K=64, H=10)
+        tr = run_oracle(wl, traj=True)["traj"]
+        nom, traj, du, dt = tr[0], tr[1:], wl.u_eps[1:], wl.dt
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64)
+    g = V.policy(ctx, t(nom), t(traj), t(du), dt, P.Q_F, P.Q_C, P.R_C, stream=_Stream())
+    o = P.policy(nom, traj, du, dt, P.Q_F, P.Q_C, P.R_C)
+    print(json.dumps({
+        "case": name, "prec": V.FP64,
+        "status_equal": bool(np.array_equal(g["status"].numpy(), o["status"])),
+        "n_rank_deficient": int(o["status"].sum()),
+        "A": rel_l2(g["a"].numpy(), o["A"]), "B": rel_l2(g["b"].numpy(), o["B"]),
+        "S": rel_l2(g["s"].numpy(), o["S"]), "gain": rel_l2(g["gain"].numpy(), o["gain"])}),
+        flush=True)
+
+
 def main(names):
     ctx = V.Context(0)
     for name in names:
+        if name.startswith("policy"):
+            policy_case(ctx, name)
+            continue
         wl = cases()[name]()
         for cls in (V.CLASS_SMALL, V.CLASS_LARGE, V.CLASS_STREAM):
             ctx.set_tuning(cls, *{V.CLASS_SMALL: (4, 64), V.CLASS_LARGE: (2, 64),

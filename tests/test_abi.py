@@ -134,3 +134,25 @@ def test_tuning_arguments_are_checked_without_a_gpu():
     t, tile = C.c_int32(), C.c_int32()
     assert L.vpm_set_tuning(None, 0, 4, 64) == V.EINVAL
     assert L.vpm_get_tuning(None, 0, C.byref(t), C.byref(tile)) == V.EINVAL
+
+
+def test_policy_arguments_are_checked_without_a_gpu():
+    L = V.lib()
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation is host-only
+    pin = V.PolicyIn(8, 5, 0.01, fake, fake, fake)
+    for i in range(7):
+        pin.q_f[i], pin.q_c[i] = 1.0, 0.1
+    pin.r_c = 0.01
+    pout = V.PolicyOut(fake, fake, fake, None, fake)
+    assert L.vpm_policy(None, C.byref(pin), C.byref(pout), None) == V.EINVAL
+    bad = [("K", 0), ("H", 0), ("dt", 0.0), ("r_c", 0.0), ("r_c", float("nan")), ("du", None)]
+    for field, value in bad:
+        b = V.PolicyIn.from_buffer_copy(pin)
+        setattr(b, field, value)
+        assert L.vpm_policy(fake, C.byref(b), C.byref(pout), None) == V.EINVAL, field
+    b = V.PolicyIn.from_buffer_copy(pin)
+    b.q_c[3] = -1.0
+    assert L.vpm_policy(fake, C.byref(b), C.byref(pout), None) == V.EINVAL
+    o = V.PolicyOut.from_buffer_copy(pout)
+    o.gain = None
+    assert L.vpm_policy(fake, C.byref(pin), C.byref(o), None) == V.EINVAL

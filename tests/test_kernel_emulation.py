@@ -46,3 +46,14 @@ def test_emulated_kernels_match_oracle(emu_lib, case):
         for key in ("traj", "gamma_s", "g_final"):
             assert row[key] <= tol, (key, row)
         assert row["wake"] <= 10 * tol, row
+
+
+@pytest.mark.parametrize("case,deficient", [("policy_linear", 1), ("policy_vpm", 0)])
+def test_emulated_policy_kernels_match_oracle(emu_lib, case, deficient):
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), case],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-3000:]
+    row = [json.loads(x) for x in r.stdout.splitlines() if x.startswith("{")][0]
+    assert row["status_equal"] and row["n_rank_deficient"] == deficient, row
+    for key in ("A", "B", "S", "gain"):
+        assert row[key] <= 1e-9, (key, row)

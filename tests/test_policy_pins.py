@@ -9,25 +9,7 @@ import pytest
 import scipy.linalg
 
 from oracle import policy as P
-
-
-def _euler_data(rng, K, H, dt, a_hats, b_hats, sx=0.02, su=0.1):
-    """Nominal trajectory (arbitrary) and K perturbed trajectories whose
-    deviations follow d(dx)/dt = A_c,k dx + B_c,k du exactly under explicit
-    Euler, with A_c,k, B_c,k built from the given blocks and the kinematic
-    rows written out here directly."""
-    nom = np.cumsum(rng.normal(size=(H + 1, 7)), axis=0)
-    dx = np.zeros((K, H + 1, 7))
-    dx[:, 0] = rng.normal(scale=sx, size=(K, 7))
-    du = rng.normal(scale=su, size=(K, H))
-    for k in range(H):
-        d = dx[:, k]
-        rate = np.zeros((K, 7))
-        rate[:, 0], rate[:, 1], rate[:, 2] = d[:, 4], d[:, 5], d[:, 6]
-        rate[:, 3] = du[:, k]
-        rate[:, 4:7] = d[:, 2:7] @ a_hats[k].T + np.outer(du[:, k], b_hats[k])
-        dx[:, k + 1] = d + dt * rate
-    return nom, nom[None] + dx, du
+from tests.policy_data import euler_linear_data as _euler_data
 
 
 def test_p18_recovers_the_linear_system_that_made_the_data():
