@@ -94,7 +94,7 @@ def lib(f32_state: bool = False):
         L.orc_segment_hits_plate.argtypes = [P, P, P, P]
         L.orc_segment_hits_plate.restype = i32
         L.orc_rollout_batch.argtypes = ([P, i32, i32, d] + [P] * 8 + [i32] + [P] * 3 + [i32, i32]
-                                        + [P] * 13)
+                                        + [P] * 16)
         L.orc_rollout_batch.restype = i32
         L.orc_cost.argtypes = [P, P, P]
         L.orc_cost.restype = d
@@ -237,13 +237,16 @@ def mppi(cost_arr, lam, mu, xi):
 def rollout_batch(params: dict, K, H, dt, g0, gb0, field_off, field_of, wx, wz, wg,
                   pairs, u, x_goal, q_diag, *, traj=False, gamma_s=False, force=False,
                   final_wake=False, vel_last=False, reverse=False, n_threads=0,
-                  rollouts=None, f32_state=False):
+                  rollouts=None, f32_state=False, fb_gain=None, fb_xref=None,
+                  gb_final=False):
     """Run the oracle on rollouts ``rollouts`` (default: all K) of a batch.
 
     Inputs follow the layout of ``orc_rollout_batch``; ``u`` is the full
     control (mean + perturbation), shape [K, H]. Returns a dict of numpy
     arrays indexed by position in ``rollouts``. ``f32_state`` runs the
-    binary32-storage variant.
+    binary32-storage variant. ``fb_gain`` [H, 7] and ``fb_xref`` [H, 7]
+    close the loop with the policy of Sec. IV-B: the control of step n is
+    u[k, n] - fb_gain[n] . (x_n - fb_xref[n]).
     """
     p = make_params(params)
     nb = params["n_bound"]
@@ -260,6 +263,10 @@ def rollout_batch(params: dict, K, H, dt, g0, gb0, field_off, field_of, wx, wz, 
     u = _f64(np.asarray(u)[idx])
     wx, wz, wg = _f64(wx), _f64(wz), _f64(wg)
     out = dict(g_final=np.zeros((k, 7)), cost=np.zeros(k), status=np.zeros(k, dtype=np.int32))
+    if gb_final:
+        out["gb_final"] = np.zeros((k, nb))
+    fbg = None if fb_gain is None else _f64(fb_gain)
+    fbx = None if fb_gain is None else _f64(fb_xref)
     if traj:
         out["traj"] = np.zeros((k, H + 1, 7))
     if gamma_s:
@@ -286,5 +293,6 @@ def rollout_batch(params: dict, K, H, dt, g0, gb0, field_off, field_of, wx, wz, 
         int(reverse), int(n_threads), _p(out["g_final"]), _p(out["cost"]), _p(out["status"]),
         _p(out.get("traj")), _p(out.get("gamma_s")), _p(out.get("force")),
         _p(out_off) if want_w else None, _p(out.get("wx")), _p(out.get("wz")), _p(out.get("wg")),
-        _p(out.get("n_final")), _p(out.get("vel_last")), _p(out.get("n_vel_last")))
+        _p(out.get("n_final")), _p(out.get("vel_last")), _p(out.get("n_vel_last")),
+        _p(fbg), _p(fbx), _p(out.get("gb_final")))
     return out

@@ -704,7 +704,8 @@ int32_t orc_rollout_batch(
     int32_t n_threads, double *g_final, double *cost, int32_t *status,
     double *traj, double *gamma_s, double *force, const int64_t *out_off,
     double *wx_out, double *wz_out, double *wg_out, int32_t *n_final,
-    double *vel_last, int32_t *n_vel_last) {
+    double *vel_last, int32_t *n_vel_last, const double *fb_gain,
+    const double *fb_xref, double *gb_final) {
   const int32_t nb = p->n_bound;
   const int32_t S = orc_system_size(nb, p->shed_mode);
 #ifdef _OPENMP
@@ -743,7 +744,16 @@ int32_t orc_rollout_batch(
       orc_loads ld;
       int32_t last = (n == H - 1);
       double *vel = (last && vel_last) ? &vel_last[2 * out_off[k]] : NULL;
-      orc_step(p, &s, dt, u[(int64_t)k * H + n], reverse,
+      /* Sec. IV-B feedback policy: u_n = u^d_n - H_n (x_n - x^d_n), with the
+       * state at the start of the step (open loop without gains) */
+      double un = u[(int64_t)k * H + n];
+      if (fb_gain) {
+        double fb = 0.0;
+        for (int32_t j = 0; j < 7; ++j)
+          fb += fb_gain[(int64_t)n * 7 + j] * (s.g[j] - fb_xref[(int64_t)n * 7 + j]);
+        un -= fb;
+      }
+      orc_step(p, &s, dt, un, reverse,
                gamma_s ? &gamma_s[((int64_t)k * H + n) * S] : NULL, &ld, vel,
                (last && n_vel_last) ? &n_vel_last[k] : NULL);
       if (force) {
@@ -762,6 +772,7 @@ int32_t orc_rollout_batch(
     if (!finite) s.status |= ORC_NONFINITE;
     cost[k] = finite ? orc_cost(s.g, x_goal, q_diag) : INFINITY;
     status[k] = s.status;
+    if (gb_final) memcpy(&gb_final[(int64_t)nb * k], s.gb_prev, sizeof(double) * nb);
     if (out_off && n_final) {
       int64_t o = out_off[k];
       int64_t capo = out_off[k + 1] - o;

@@ -131,7 +131,8 @@ int32_t orc_rollout_batch(
     int32_t n_threads, double *g_final, double *cost, int32_t *status,
     double *traj, double *gamma_s, double *force, const int64_t *out_off,
     double *wx_out, double *wz_out, double *wg_out, int32_t *n_final,
-    double *vel_last, int32_t *n_vel_last);
+    double *vel_last, int32_t *n_vel_last, const double *fb_gain,
+    const double *fb_xref, double *gb_final);
 
 /* Terminal cost (Eq. 24): J = sum_k q_k (g_k - x_goal_k)^2. */
 double orc_cost(const double *g_final, const double *x_goal,

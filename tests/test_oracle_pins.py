@@ -566,3 +566,53 @@ def test_p17_gate_always_open_or_closed_reduces_to_the_fixed_modes():
         for k in range(wl.K):
             assert np.array_equal(wake(got, k), wake(want, k))
     assert te["n_final"][0] == wl.n0[0] + wl.H and both["n_final"][0] == wl.n0[0] + 2 * wl.H
+
+
+# ------------------------------ P20 closed loop under the policy (Sec. IV-B)
+
+def _closed_loop(gain, xref, u, g0, H, dt=0.005, nb=16):
+    p = base_params(nb, decay=0.0, n_wake_max=0)
+    return O.rollout_batch(p, 1, H, dt, np.array([g0]), np.zeros((1, nb)),
+                           np.array([0, 0], dtype=np.int64), None, np.zeros(0), np.zeros(0),
+                           np.zeros(0), None, np.array([u]), W.X_GOAL, W.Q_POS_PITCH,
+                           traj=True, gamma_s=True, gb_final=True, fb_gain=gain, fb_xref=xref)
+
+
+def test_p20_feedback_on_phi_decays_geometrically():
+    # u = -kappa (phi - 0) and phi_{n+1} = phi_n + dt u: phi_n = phi_0 (1 - kappa dt)^n
+    H, dt, kappa = 40, 0.005, 7.0
+    gain = np.zeros((H, 7))
+    gain[:, 3] = kappa
+    out = _closed_loop(gain, np.zeros((H, 7)), np.zeros(H), [0, 0, 0, 0.1, 6.0, 0, 0], H, dt)
+    phi = out["traj"][0, :, 3]
+    np.testing.assert_allclose(phi, 0.1 * (1 - kappa * dt) ** np.arange(H + 1), rtol=1e-13)
+
+
+def test_p20_feedback_uses_the_state_and_reference_at_the_start_of_each_step():
+    # gain on theta only: phi_{n+1} - phi_n = dt (u_n - kappa (theta_n - theta_ref_n))
+    rng = np.random.default_rng(0)
+    H, dt, kappa = 30, 0.005, 3.0
+    gain = np.zeros((H, 7))
+    gain[:, 2] = kappa
+    xref = np.zeros((H, 7))
+    xref[:, 2] = rng.normal(scale=0.05, size=H)
+    u = rng.normal(scale=0.2, size=H)
+    out = _closed_loop(gain, xref, u, [0, 0, 0.05, 0, 6.0, 0, 0.3], H, dt)
+    tr = out["traj"][0]
+    dphi = tr[1:, 3] - tr[:-1, 3]
+    np.testing.assert_allclose(dphi, dt * (u - kappa * (tr[:-1, 2] - xref[:, 2])),
+                               rtol=0, atol=1e-15)
+
+
+def test_p20_zero_gain_is_the_open_loop_and_gb_final_is_the_last_solve():
+    H, nb = 20, 16
+    u = 0.3 * np.sin(np.arange(H))
+    g0 = [0, 0, 0.05, 0, 6.0, 0, 0]
+    closed = _closed_loop(np.zeros((H, 7)), np.zeros((H, 7)), u, g0, H, nb=nb)
+    p = base_params(nb, decay=0.0, n_wake_max=0)
+    open_ = O.rollout_batch(p, 1, H, 0.005, np.array([g0]), np.zeros((1, nb)),
+                            np.array([0, 0], dtype=np.int64), None, np.zeros(0), np.zeros(0),
+                            np.zeros(0), None, np.array([u]), W.X_GOAL, W.Q_POS_PITCH, traj=True)
+    assert np.array_equal(closed["traj"], open_["traj"])
+    # the carried previous-step bound circulations are those of the last solve
+    assert np.array_equal(closed["gb_final"][0], closed["gamma_s"][0, H - 1, :nb])
