@@ -121,6 +121,12 @@ typedef struct {
                              step n is u_mean[n] + u_eps[k][n]              */
   double x_goal[7];       /* host values: goal state of the cost (Eq. 24)   */
   double q_diag[7];       /* host values: diagonal of Q (Eq. 24)            */
+  const double *fb_gain;  /* [H][7] feedback gains H_n of the policy of
+                             Sec. IV-B, or NULL (open loop); with gains the
+                             control of step n is u_mean[n] + u_eps[k][n]
+                             - fb_gain[n] . (x_n - fb_xref[n]), x_n the
+                             state at the start of the step (FP64)          */
+  const double *fb_xref;  /* [H][7] reference states x^d_n (with fb_gain)   */
 } vpm_batch_in;
 
 /* Outputs of vpm_rollout_batch. Required: g_final, cost, status. Optional
@@ -149,6 +155,10 @@ typedef struct {
                              advected in the last step (FIFO order, before
                              merging), or NULL                              */
   int32_t *n_vel_last;    /* [K] count of vel_last entries, or NULL         */
+  double *gb_final;       /* [K][N_b] bound circulations of the last step
+                             (the gb0 that continues the rollout), or NULL;
+                             a rollout with a status bit of its input
+                             (capacity, bad field) gets its gb0             */
 } vpm_batch_out;
 
 typedef struct vpm_ctx vpm_ctx;

@@ -84,6 +84,8 @@ VPM_API int vpm_validate_batch(const vpm_params *p, const vpm_batch_in *in,
     return fail(VPM_EINVAL, "a required input pointer is NULL");
   if (!in->field_of && in->n_fields < in->K)
     return fail(VPM_EINVAL, "field_of is NULL but n_fields < K");
+  if ((in->fb_gain == nullptr) != (in->fb_xref == nullptr))
+    return fail(VPM_EINVAL, "fb_gain and fb_xref go together");
   for (int i = 0; i < 7; ++i)
     if (!std::isfinite(in->x_goal[i]) || !std::isfinite(in->q_diag[i]))
       return fail(VPM_EINVAL, "non-finite x_goal or q_diag");

@@ -67,6 +67,8 @@ struct KArgs {
   double x_goal[7], q_diag[7];
   const double *g0, *gb0, *wx, *wz, *wg, *u_mean, *u_eps, *kinv_t;
   const double *kinv_te;  // trailing-edge-only inverse (gate on), after kinv_t in LDS
+  const double *fb_gain, *fb_xref;  // closed-loop policy [H][7] each, or NULL
+  double *gb_final;
   const int64_t *field_off;
   const int32_t *field_of, *pairs;
   double *g_final, *cost, *traj, *gamma_s, *wx_out, *wz_out, *wg_out;
@@ -92,6 +94,7 @@ template <typename R> struct Shared {
   int claimed;  // rollout claimed from the work queue
   int slot;     // issue-priority slot of this workgroup (see rotate_priority)
   int mode_step, n_shed;  // this step's shedding mode and vortices shed
+  double u_fb;            // this step's feedback control term (0 open loop)
   int pa[kMaxPairs], pb[kMaxPairs];
   long long pairs;
 };
@@ -275,8 +278,16 @@ __device__ __noinline__ double wing_aoa(double th, double xd, double zd, double 
 // the call (a call alone changes the register allocation of the kernel).
 template <typename R, bool GATE>
 __device__ void prologue(const KArgs &a, Shared<R> &sh,
-                         typename SrcOf<R>::type *src) {
+                         typename SrcOf<R>::type *src, int n) {
   geometry(a, sh);
+  // Sec. IV-B policy: u_n = u^d_n - H_n (x_n - x^d_n) from the state at the
+  // start of the step, in FP64
+  double fb = 0.0;
+  if (a.fb_gain) {
+    const double *hn = a.fb_gain + (size_t)n * 7, *xn = a.fb_xref + (size_t)n * 7;
+    for (int j = 0; j < 7; ++j) fb += hn[j] * (double(sh.g[j]) - xn[j]);
+  }
+  sh.u_fb = -fb;
   int mode = a.mode;
   // Sec. III-A separation gate: the leading edge sheds only while the wing's
   // angle of attack exceeds the critical angle; decided in FP64 from the
@@ -317,6 +328,8 @@ __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *sr
       if (a.pair_count) a.pair_count[k] = 0;
       if (a.n_final) a.n_final[k] = 0;
       if (a.n_vel_last) a.n_vel_last[k] = 0;
+      if (a.gb_final)
+        for (int j = 0; j < a.nb; ++j) a.gb_final[(size_t)k * a.nb + j] = a.gb0[(size_t)k * a.nb + j];
     }
     return false;
   }
@@ -611,7 +624,7 @@ __device__ void epilogue(const KArgs &a, Shared<R> &sh,
     for (int i = 0; i < 7; ++i)
       a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
   if (last && a.n_vel_last) a.n_vel_last[k] = m;
-  if (!last) prologue<R, GATE>(a, sh, src);
+  if (!last) prologue<R, GATE>(a, sh, src, n + 1);
 }
 
 // Final outputs of rollout k.
@@ -634,6 +647,7 @@ __device__ void finish(const KArgs &a, const Shared<R> &sh,
     if (a.pair_count) a.pair_count[k] = sh.pairs;
     if (a.n_final) a.n_final[k] = sh.n_w;
   }
+  if (a.gb_final && tid < a.nb) a.gb_final[(size_t)k * a.nb + tid] = sh.gb_prev[tid];
   if (a.wake_off) {
     const int64_t o = a.wake_off[k];
     const int capo = static_cast<int>(a.wake_off[k + 1] - o);
@@ -778,7 +792,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, GATE>(a, sh, src);
+        if (tid == 0) prologue<R, GATE>(a, sh, src, 0);
         __syncthreads();
       }
       rotate_priority(sh.slot, n);
@@ -831,7 +845,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       }
 
       if (wave == 0)
-        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e);
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e + sh.u_fb);
       __syncthreads();
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
@@ -916,7 +930,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     __syncthreads();
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, GATE>(a, sh, src);
+        if (tid == 0) prologue<R, GATE>(a, sh, src, 0);
         __syncthreads();
       }
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
@@ -940,7 +954,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       }
       __syncthreads();
       if (wave == 0)
-        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e);
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e + sh.u_fb);
       __syncthreads();
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
@@ -1384,6 +1398,9 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.wg_out = wake ? out->wg : nullptr;
   a.vel_last = wake ? out->vel_last : nullptr;
   a.n_vel_last = out->n_vel_last;
+  a.gb_final = out->gb_final;
+  a.fb_gain = in->fb_gain;
+  a.fb_xref = in->fb_gain ? in->fb_xref : nullptr;
   if (p->precision == VPM_FP64)
     return run_batch<double, 2, 8>(ctx, a, ctx->path, stream);
   return run_batch<float, 4, 16>(ctx, a, ctx->path, stream);

@@ -42,13 +42,14 @@ class BatchIn(C.Structure):
     _fields_ = [("K", _I), ("H", _I), ("dt", _D), ("n_fields", _I), ("max_wake0", _I),
                 ("n_pairs", _I), ("reserved", _I), ("g0", _P), ("gb0", _P), ("field_off", _P),
                 ("field_of", _P), ("wx", _P), ("wz", _P), ("wg", _P), ("pairs", _P),
-                ("u_mean", _P), ("u_eps", _P), ("x_goal", _D * 7), ("q_diag", _D * 7)]
+                ("u_mean", _P), ("u_eps", _P), ("x_goal", _D * 7), ("q_diag", _D * 7),
+                ("fb_gain", _P), ("fb_xref", _P)]
 
 
 class BatchOut(C.Structure):
     _fields_ = [("g_final", _P), ("cost", _P), ("status", _P), ("traj", _P), ("gamma_s", _P),
                 ("pair_count", _P), ("wake_off", _P), ("wx", _P), ("wz", _P), ("wg", _P),
-                ("n_final", _P), ("vel_last", _P), ("n_vel_last", _P)]
+                ("n_final", _P), ("vel_last", _P), ("n_vel_last", _P), ("gb_final", _P)]
 
 
 _lib = None
@@ -153,6 +154,18 @@ class DeviceBatch:
         self.n_fields = len(wl.field_off) - 1
         sizes = np.diff(wl.field_off)
         self.max_wake0 = int(sizes.max()) if sizes.size else 0
+        self.fb_gain = self.fb_xref = None
+
+    def set_feedback(self, gain, xref):
+        """Close the loop with the policy's gains [H, 7] and reference states
+        [H, 7] (float64 device tensors), or open it again with None."""
+        if gain is None:
+            self.fb_gain = self.fb_xref = None
+            return
+        for t in (gain, xref):
+            if t.dtype.itemsize != 8 or tuple(t.shape) != (self.H, 7) or not t.is_contiguous():
+                raise ValueError("feedback gains and references must be contiguous float64 [H, 7]")
+        self.fb_gain, self.fb_xref = gain, xref
 
     def batch_in(self, k0=0, k1=None) -> BatchIn:
         """The ABI input struct for rollouts [k0, k1) of this batch."""
@@ -166,6 +179,7 @@ class DeviceBatch:
         b.wx, b.wz, b.wg = _ptr(self.wx), _ptr(self.wz), _ptr(self.wg)
         b.pairs = _ptr(self.pairs, 2 * self.n_pairs * k0)
         b.u_mean, b.u_eps = _ptr(self.u_mean), _ptr(self.u_eps, self.H * k0)
+        b.fb_gain, b.fb_xref = _ptr(self.fb_gain), _ptr(self.fb_xref)
         for i in range(7):
             b.x_goal[i] = float(self.wl.x_goal[i])
             b.q_diag[i] = float(self.wl.q_diag[i])
@@ -176,7 +190,7 @@ class DeviceOutputs:
     """Output buffers of one rollout batch (torch tensors on the GPU)."""
 
     def __init__(self, db: DeviceBatch, *, traj=False, gamma_s=False, pair_count=True,
-                 final_wake=False, vel_last=False, device="cuda"):
+                 final_wake=False, vel_last=False, gb_final=False, device="cuda"):
         import torch
         K, H = db.K, db.H
         nb = db.wl.params["n_bound"]
@@ -188,6 +202,7 @@ class DeviceOutputs:
         S = nb + _SHED_UNKNOWNS[db.wl.params.get("shed_mode", SHED_BOTH)]
         self.gamma_s = torch.empty((K, H, S), **f64) if gamma_s else None
         self.pair_count = torch.empty(K, dtype=torch.int64, device=device) if pair_count else None
+        self.gb_final = torch.empty((K, nb), **f64) if gb_final else None
         self.wake_off = self.wx = self.wz = self.wg = self.n_final = None
         self.vel_last = self.n_vel_last = None
         if final_wake or vel_last:
@@ -214,7 +229,8 @@ class DeviceOutputs:
             for name, _ in BatchOut._fields_:
                 setattr(o, name, _ptr(getattr(self, name)))
             return o
-        per = dict(g_final=7, cost=1, status=1, pair_count=1)
+        per = dict(g_final=7, cost=1, status=1, pair_count=1, gb_final=self.gb_final.shape[1]
+                   if self.gb_final is not None else 0)
         for name, width in per.items():
             setattr(o, name, _ptr(getattr(self, name), width * k0))
         return o
@@ -222,7 +238,7 @@ class DeviceOutputs:
     def to_numpy(self) -> dict:
         out = {}
         for name in ("g_final", "cost", "status", "traj", "gamma_s", "pair_count", "wx", "wz",
-                     "wg", "n_final", "vel_last", "n_vel_last"):
+                     "wg", "n_final", "vel_last", "n_vel_last", "gb_final"):
             t = getattr(self, name)
             if t is not None:
                 out[name] = t.cpu().numpy()

@@ -49,6 +49,8 @@ def cases():
                                          shed_mode=W.SHED_NONE),
         # separation gate switching between both-edge and trailing-edge steps
         "gated": lambda: gated_at_median(W.realtime(K=4, H=8)),
+        # closed loop under feedback gains (the policy inside the rollout)
+        "feedback": lambda: W.realtime(K=3, H=6),
     }
 
 
@@ -96,10 +98,19 @@ def main(names):
                                   V.CLASS_STREAM: (4, 64)}[cls])
         for cls, t, tile in TUNINGS.get(name, []):
             ctx.set_tuning(cls, t, tile)
-        o = run_oracle(wl, traj=True, final_wake=True, gamma_s=True)
+        fb = {}
+        if name == "feedback":
+            rng = np.random.default_rng(0)
+            fb = dict(fb_gain=rng.normal(scale=0.5, size=(wl.H, 7)),
+                      fb_xref=np.repeat(wl.g0[:1], wl.H, axis=0))
+        o = run_oracle(wl, traj=True, final_wake=True, gamma_s=True, gb_final=True, **fb)
         for prec in (V.FP32C, V.FP64):
             db = V.DeviceBatch(wl, device="cpu")
-            out = V.DeviceOutputs(db, device="cpu", traj=True, final_wake=True, gamma_s=True)
+            if fb:
+                import torch
+                db.set_feedback(torch.tensor(fb["fb_gain"]), torch.tensor(fb["fb_xref"]))
+            out = V.DeviceOutputs(db, device="cpu", traj=True, final_wake=True, gamma_s=True,
+                                  gb_final=True)
             ctx.rollout(wl.params, db, out, prec, stream=_Stream())
             g = out.to_numpy()
             wake = max((rel_l2(a, b) for k in range(wl.K)
@@ -109,6 +120,7 @@ def main(names):
                 "traj": rel_l2(g["traj"], o["traj"]),
                 "gamma_s": rel_l2(g["gamma_s"], o["gamma_s"]),
                 "g_final": rel_l2(g["g_final"], o["g_final"]),
+                "gb_final": rel_l2(g["gb_final"], o["gb_final"]),
                 "wake": wake,
                 "n_final_equal": bool(np.array_equal(g["n_final"], o["n_final"])),
                 "gate_margin": gate_margin(wl, o["traj"]) if wl.params.get("gate") else None,
