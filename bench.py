@@ -19,6 +19,11 @@ Workloads (``--workload``):
                       perturbed FP64 rollouts of 77 steps (dt = 10 ms) and
                       the TVLQR recursion; one step = one vpm_policy call on
                       resident trajectories
+  replan              one replanning cycle of the nonlinear MPC (Sec. IV-C)
+                      at the paper's controller size: projection by 10 steps
+                      under the policy in force, 3 MPPI iterations of 256
+                      rollouts x 77 steps, 257 policy rollouts and the
+                      policy; one step = one vpm_replan call
 The default run also replays the first requests of the serving trace through
 the replanning service (8 slots) and through the plain one-at-a-time path,
 reporting p50/p99 latency and rollouts/s for both. Prints one JSON line.
@@ -47,7 +52,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress", "policy"],
+    ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress", "policy",
+                                           "replan"],
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -443,6 +449,92 @@ def policy_main(args):
     print(json.dumps(line), flush=True)
 
 
+def replan_main(args):
+    import torch
+
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    steps = 30 if args.steps is None else args.steps
+    warmup = 3 if args.warmup is None else args.warmup
+    prec_name = args.precision or "fp32c"
+    prec = V.FP32C if prec_name == "fp32c" else V.FP64
+    c = W.replan_case()
+    ctx = V.Context(0)
+    tuning = apply_tuning(ctx, args.tuning)
+    dev = lambda a: None if a is None else torch.tensor(
+        np.ascontiguousarray(a), device="cuda",
+        dtype=torch.int32 if np.asarray(a).dtype == np.int32 else torch.float64)
+    state = tuple(dev(c[k]) for k in ("g", "gb", "wx", "wz", "wg", "pairs"))
+    args_d = (dev(c["u_eps"]), dev(c["x_eps"]), dev(c["du"]))
+    stream = torch.cuda.current_stream()
+
+    def cycle(plan):
+        return V.replan(ctx, c["params"], prec, c["dt"], state, plan, *args_d, c["lam"],
+                        c["x_goal"], c["q_diag"], c["q_f"], c["q_c"], c["r_c"], c["P"],
+                        stream=stream)
+    # the first cycle projects open loop; later cycles project under the
+    # policy the previous cycle produced (same resident state each time)
+    out = cycle((dev(c["u_plan"]), None, None))
+    for _ in range(warmup):
+        out = cycle((out["u_new"].clone(), out["x_new"][:-1].contiguous(), out["gain"].clone()))
+    torch.cuda.synchronize()
+    plan = (out["u_new"].clone(), out["x_new"][:-1].contiguous(), out["gain"].clone())
+    evs, walls = [], []
+    for _ in range(steps):
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        out = cycle(plan)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        walls.append(1e3 * (time.perf_counter() - t0))
+        evs.append(ev)
+    each = [a.elapsed_time(b) for a, b in evs]
+    H, K, I, Kp, P = c["H"], c["K"], c["iterations"], c["Kp"], c["P"]
+    ms = float(np.mean(walls))
+    line = {
+        "metric": "replanning-cycle latency (projection + MPPI iterations + LS-TVLQR policy)",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == V.FP32C else "f64", "data": "synthetic",
+        "config": {"workload": "replan: project %d steps, %d MPPI iterations of K=%d x H=%d, "
+                               "%d policy rollouts, dt=10 ms, N_b=32, one disturbance pair"
+                               % (P, I, K, H, Kp + 1), "K": K, "H": H, "P": P,
+                   "iterations": I, "Kp": Kp, "precision": prec_name},
+        "latency_ms_p50": float(np.percentile(walls, 50)),
+        "latency_ms_p99": float(np.percentile(walls, 99)),
+        "gpu_ms_mean": float(np.mean(each)),
+        "replan_budget_ms": 100.0,
+        "rollouts_per_cycle": 1 + I * K + Kp + 1,
+        "argmin_last": out["argmin"].cpu().tolist(),
+        "tuning": tuning,
+        "kernel_timing": "HIP events around each vpm_replan call on its stream; wall time "
+                         "from the call to its completion",
+        "gpu_clock_after_timed_region": gpu_clock(),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import replan as OR
+        u_plan, x_plan, gain_plan = (t.cpu().numpy() for t in plan)
+        t0 = time.perf_counter()
+        o = OR.replan(c["params"], c["dt"], c["g"], c["gb"], c["wx"], c["wz"], c["wg"],
+                      c["pairs"], u_plan, x_plan, gain_plan, P, c["u_eps"], c["x_eps"], c["du"],
+                      c["lam"], c["x_goal"], c["q_diag"], c["q_f"], c["q_c"], c["r_c"])
+        cpu_ms = 1e3 * (time.perf_counter() - t0)
+        line["cpu_baseline"] = {"value": cpu_ms, "unit": "ms",
+                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+                                "kind": "oracle",
+                                "sample": "one whole cycle (FP64, OpenMP over rollouts)"}
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        line["error_vs_oracle"] = {
+            "precision": prec_name,
+            "argmin_equal": bool(np.array_equal(g["argmin"], o["argmin"])),
+            "u_new_rel_l2": _rel_l2(g["u_new"], o["u_new"]),
+            "x_new_rel_l2": _rel_l2(g["x_new"], o["x_new"]),
+            "gain_rel_l2": _rel_l2(g["gain"], o["gain"])}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -452,6 +544,8 @@ def main():
         sys.exit(2)
     if args.workload == "policy":
         return policy_main(args)
+    if args.workload == "replan":
+        return replan_main(args)
     import torch
 
     from paper_2509_16079_amd import vpm as V

@@ -392,6 +392,65 @@ typedef struct {
 VPM_API int vpm_policy(vpm_ctx *ctx, const vpm_policy_in *in, vpm_policy_out *out,
                        void *stream);
 
+/* One replanning cycle of the nonlinear MPC of Sec. IV-C, enqueued on one
+ * stream with no host round trip:
+ *  1. projection: the resident state (glider, bound circulations, wake) is
+ *     stepped P steps forward under the policy in force, u_n = u_plan[n] -
+ *     gain_plan[n] . (x_n - x_plan[n]) (open loop when gain_plan is NULL),
+ *     to where the new plan will take over;
+ *  2. MPPI: `iterations` rounds of K rollouts of H steps from the projected
+ *     state around the mean controls, the first mean being u_plan shifted
+ *     by P (its last value held), each round followed by the reweighting of
+ *     Eq. 25 (perturbations u_eps[iteration][k][n] are inputs);
+ *  3. policy: the nominal rollout under the final mean and Kp rollouts from
+ *     perturbed projected states (g_proj + x_eps[i]) under perturbed
+ *     controls (+ du[i]), then vpm_policy on their trajectories.
+ * The projection and MPPI rollouts run in params->precision, the policy
+ * rollouts in FP64 (the regression takes differences of trajectories about
+ * 1e-2 apart, which binary32 state storage would blur). Disturbance pairs (indices into
+ * the resident wake) are only accepted when no merging can occur within
+ * P + H steps (n_wake_max = 0 or n_wake + 2 (P + H) <= n_wake_max), so that
+ * their indices stay valid in the projected wake. The context keeps a
+ * workspace for the cycle, grown on demand (a growth synchronises the
+ * device). Errors: VPM_EINVAL, VPM_ENOMEM, VPM_ESINGULAR, VPM_EDEVICE. */
+typedef struct {
+  double dt;              /* step [s] (> 0)                                  */
+  int32_t H;              /* plan horizon in steps (>= 1)                    */
+  int32_t P;              /* projection steps (0 <= P <= H)                  */
+  int32_t K;              /* MPPI rollouts per iteration (>= 1)              */
+  int32_t iterations;     /* MPPI iterations (>= 1)                          */
+  int32_t Kp;             /* perturbed rollouts of the policy synthesis      */
+  int32_t n_wake;         /* resident wake vortices (>= 0)                   */
+  int32_t n_pairs;        /* disturbance pairs (0..4)                        */
+  int32_t reserved;
+  const double *g;        /* device [7] resident glider state                */
+  const double *gb;       /* device [N_b] its previous bound circulations    */
+  const double *wx, *wz, *wg; /* device [n_wake] resident wake, oldest first */
+  const int32_t *pairs;   /* device [2 n_pairs] or NULL                      */
+  const double *u_plan;   /* device [H] controls of the policy in force      */
+  const double *x_plan;   /* device [H][7] its nominal states, or NULL       */
+  const double *gain_plan; /* device [H][7] its gains, or NULL (open loop)   */
+  const double *u_eps;    /* device [iterations][K][H] MPPI perturbations    */
+  const double *x_eps;    /* device [Kp][7] initial-state perturbations      */
+  const double *du;       /* device [Kp][H] control perturbations            */
+  double lambda;          /* MPPI temperature (> 0)                          */
+  double x_goal[7], q_diag[7]; /* host: cost of Eq. 24                       */
+  double q_f[7], q_c[7], r_c;  /* host: TVLQR weights (vpm_policy)           */
+} vpm_replan_in;
+
+typedef struct {
+  double *g_proj;         /* device [7] projected glider state               */
+  double *u_new;          /* device [H] new nominal controls                 */
+  double *x_new;          /* device [H+1][7] new nominal trajectory          */
+  double *gain;           /* device [H][7] new TVLQR gains                   */
+  double *jmin;           /* device [iterations] best cost of each round     */
+  int32_t *argmin;        /* device [iterations] its rollout                 */
+  int32_t *status;        /* device [H] rank-deficient steps of the policy   */
+} vpm_replan_out;
+
+VPM_API int vpm_replan(vpm_ctx *ctx, const vpm_params *params, const vpm_replan_in *in,
+                       vpm_replan_out *out, void *stream);
+
 /* Exact pair-interaction count of one rollout (host arithmetic): per step
  * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b
  * bound pairs with N_w' = N_w + 2 (both edges shed), merging above

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvpm.so")
 SOURCES = ["api.hip", "plate_system.cpp", "rollout.hip", "solve_mppi.hip", "planner.hip",
-           "policy.hip"]
+           "policy.hip", "replan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -148,6 +148,7 @@ VPM_API void vpm_destroy(vpm_ctx *ctx) {
   for (auto &kv : ctx->plate_cache) (void)hipFree(kv.second);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->plan) (void)hipFree(ctx->plan);
+  if (ctx->replan) (void)hipFree(ctx->replan);
   if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
   if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
   for (int i = 0; i < 3; ++i) {
@@ -269,6 +270,15 @@ VPM_API int vpm_policy(vpm_ctx *ctx, const vpm_policy_in *in, vpm_policy_out *ou
     return fail(VPM_EINVAL, "a required output pointer is NULL");
   VPM_HIP_TRY(hipSetDevice(ctx->device));
   return vpm::launch_policy(in, out, static_cast<hipStream_t>(stream));
+}
+
+VPM_API int vpm_replan(vpm_ctx *ctx, const vpm_params *params, const vpm_replan_in *in,
+                       vpm_replan_out *out, void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  int rc = vpm::check_params(params);
+  if (rc == VPM_OK) rc = vpm::check_replan(params, in, out);
+  if (rc != VPM_OK) return rc;
+  return vpm::run_replan(ctx, params, in, out, static_cast<hipStream_t>(stream));
 }
 
 VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,

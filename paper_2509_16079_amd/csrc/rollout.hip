@@ -274,27 +274,33 @@ __device__ __noinline__ double wing_aoa(double th, double xd, double zd, double 
   return th - atan2(zdw, xdw);
 }
 
-// GATE: the separation gate is on; only the gated kernel instances contain
-// the call (a call alone changes the register allocation of the kernel).
-template <typename R, bool GATE>
+// EXT: the step's control or shedding mode depends on the state (feedback
+// policy or separation gate on). Only those kernel instances contain that
+// code: it raises the register pressure of the whole kernel (and the gate's
+// out-of-line call alone changes its register allocation), which costs the
+// plain open-loop instances a few per cent.
+template <typename R, bool EXT>
 __device__ void prologue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src, int n) {
   geometry(a, sh);
-  // Sec. IV-B policy: u_n = u^d_n - H_n (x_n - x^d_n) from the state at the
-  // start of the step, in FP64
-  double fb = 0.0;
-  if (a.fb_gain) {
-    const double *hn = a.fb_gain + (size_t)n * 7, *xn = a.fb_xref + (size_t)n * 7;
-    for (int j = 0; j < 7; ++j) fb += hn[j] * (double(sh.g[j]) - xn[j]);
-  }
-  sh.u_fb = -fb;
   int mode = a.mode;
-  // Sec. III-A separation gate: the leading edge sheds only while the wing's
-  // angle of attack exceeds the critical angle; decided in FP64 from the
-  // stored state
-  if constexpr (GATE)
-    mode = wing_aoa(sh.g[2], sh.g[4], sh.g[5], sh.g[6], a.l_wing) > a.alpha_crit ? VPM_SHED_BOTH
-                                                                            : VPM_SHED_TE;
+  if constexpr (EXT) {
+    // Sec. IV-B policy: u_n = u^d_n - H_n (x_n - x^d_n) from the state at
+    // the start of the step, in FP64
+    double fb = 0.0;
+    if (a.fb_gain) {
+      const double *hn = a.fb_gain + (size_t)n * 7, *xn = a.fb_xref + (size_t)n * 7;
+      for (int j = 0; j < 7; ++j) fb += hn[j] * (double(sh.g[j]) - xn[j]);
+    }
+    sh.u_fb = -fb;
+    // Sec. III-A separation gate: the leading edge sheds only while the
+    // wing's angle of attack exceeds the critical angle; decided in FP64 from
+    // the stored state
+    if (a.gate)
+      mode = wing_aoa(sh.g[2], sh.g[4], sh.g[5], sh.g[6], a.l_wing) > a.alpha_crit
+                 ? VPM_SHED_BOTH
+                 : VPM_SHED_TE;
+  }
   sh.mode_step = mode;
   sh.n_shed = mode == VPM_SHED_BOTH ? 2 : mode == VPM_SHED_TE ? 1 : 0;
   for (int q = 0; q < kMaxPairs; ++q) {
@@ -600,7 +606,7 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
 
 // Thread 0 at the end of a step: merging and the glider step; then, unless
 // it is the last step, the next step's prologue.
-template <typename R, bool GATE>
+template <typename R, bool EXT>
 __device__ void epilogue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src, int k, int n, int n_w) {
   using Src = typename SrcOf<R>::type;
@@ -624,7 +630,7 @@ __device__ void epilogue(const KArgs &a, Shared<R> &sh,
     for (int i = 0; i < 7; ++i)
       a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
   if (last && a.n_vel_last) a.n_vel_last[k] = m;
-  if (!last) prologue<R, GATE>(a, sh, src, n + 1);
+  if (!last) prologue<R, EXT>(a, sh, src, n + 1);
 }
 
 // Final outputs of rollout k.
@@ -763,7 +769,7 @@ __device__ inline void stage_inverses(const KArgs &a, double *kinv, int tid, int
 // LDS-resident rollout kernel, NW waves per workgroup. Pass A splits the
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
-template <typename R, int TMAX, int MINW, int NW, int TILE, bool GATE>
+template <typename R, int TMAX, int MINW, int NW, int TILE, bool EXT>
 __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
@@ -792,7 +798,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, GATE>(a, sh, src, 0);
+        if (tid == 0) prologue<R, EXT>(a, sh, src, 0);
         __syncthreads();
       }
       rotate_priority(sh.slot, n);
@@ -845,12 +851,13 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       }
 
       if (wave == 0)
-        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e + sh.u_fb);
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
+                      EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, GATE>(a, sh, src, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(a, sh, src, k, n, n_w);
       __syncthreads();
     }
     finish(a, sh, src, k, tid, kThr);
@@ -896,7 +903,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
 // Persistent: each workgroup keeps its rollout's wake in workspace slot
 // blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
 // or, with a queue, claims them in planned order.
-template <typename R, int TMAX, int NW, int TILE, bool GATE>
+template <typename R, int TMAX, int NW, int TILE, bool EXT>
 __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
@@ -930,7 +937,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     __syncthreads();
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, GATE>(a, sh, src, 0);
+        if (tid == 0) prologue<R, EXT>(a, sh, src, 0);
         __syncthreads();
       }
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
@@ -954,12 +961,13 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       }
       __syncthreads();
       if (wave == 0)
-        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane, u_m + u_e + sh.u_fb);
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
+                      EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
       pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, GATE>(a, sh, src, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(a, sh, src, k, n, n_w);
       __syncthreads();
     }
     finish(a, sh, src, k, tid, kThr);
@@ -1082,8 +1090,8 @@ int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
                                    " does not fit the LDS-resident kernel");
-  auto kern = a.gate ? rollout_lds_kernel<R, TMAX, MINW, NW, TILE, true>
-                     : rollout_lds_kernel<R, TMAX, MINW, NW, TILE, false>;
+  auto kern = a.gate || a.fb_gain ? rollout_lds_kernel<R, TMAX, MINW, NW, TILE, true>
+                                 : rollout_lds_kernel<R, TMAX, MINW, NW, TILE, false>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a, qu);
@@ -1091,28 +1099,6 @@ int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
   return VPM_OK;
 }
 
-// Grow a context buffer to `bytes` (device-synchronises before freeing a
-// smaller one). Under graph capture nothing may be allocated: the buffer must
-// already have been grown by an eager call of the same shape.
-int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what,
-                  bool capturing) {
-  if (*have >= bytes) return VPM_OK;
-  if (capturing)
-    return fail(VPM_EINVAL, std::string("the ") + what +
-                                " must be sized by an eager call before graph capture");
-  if (*buf) {
-    VPM_HIP_TRY(hipDeviceSynchronize());
-    VPM_HIP_TRY(hipFree(*buf));
-    *buf = nullptr;
-    *have = 0;
-  }
-  if (hipMalloc(buf, bytes) != hipSuccess) {
-    *buf = nullptr;
-    return fail(VPM_ENOMEM, std::string("hipMalloc of the ") + what + " failed");
-  }
-  *have = bytes;
-  return VPM_OK;
-}
 
 template <typename R, int TMAX, int NW, int TILE>
 int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
@@ -1120,8 +1106,8 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
   const int lds = stream_layout<R>(a.nb, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
-  auto kern = a.gate ? rollout_stream_kernel<R, TMAX, NW, TILE, true>
-                     : rollout_stream_kernel<R, TMAX, NW, TILE, false>;
+  auto kern = a.gate || a.fb_gain ? rollout_stream_kernel<R, TMAX, NW, TILE, true>
+                                 : rollout_stream_kernel<R, TMAX, NW, TILE, false>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
   const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
@@ -1295,6 +1281,29 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 }
 
 }  // namespace
+
+// Grow a context buffer to `bytes` (device-synchronises before freeing a
+// smaller one). Under graph capture nothing may be allocated: the buffer must
+// already have been grown by an eager call of the same shape.
+int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what,
+                  bool capturing) {
+  if (*have >= bytes) return VPM_OK;
+  if (capturing)
+    return fail(VPM_EINVAL, std::string("the ") + what +
+                                " must be sized by an eager call before graph capture");
+  if (*buf) {
+    VPM_HIP_TRY(hipDeviceSynchronize());
+    VPM_HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+  }
+  if (hipMalloc(buf, bytes) != hipSuccess) {
+    *buf = nullptr;
+    return fail(VPM_ENOMEM, std::string("hipMalloc of the ") + what + " failed");
+  }
+  *have = bytes;
+  return VPM_OK;
+}
 
 // Grow the context buffers that a batch of these sizes would need (the same
 // class decisions as run_batch), outside any stream capture.

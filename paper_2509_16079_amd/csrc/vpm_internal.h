@@ -83,6 +83,10 @@ struct vpm_ctx {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t fork_event = nullptr;
   hipEvent_t join_event[3] = {nullptr, nullptr, nullptr};
+  // replanning-cycle workspace (vpm_replan), grown on demand
+  std::mutex replan_mu;
+  void *replan = nullptr;
+  size_t replan_bytes = 0;
 };
 
 namespace vpm {
@@ -114,6 +118,12 @@ int launch_plate_solve(const vpm_params *p, int B, const double *pose,
                        const double *kinv_t, double *gamma_s,
                        hipStream_t stream);
 int launch_policy(const vpm_policy_in *in, vpm_policy_out *out, hipStream_t stream);
+// Host-only argument check of vpm_replan (no device access).
+int check_replan(const vpm_params *p, const vpm_replan_in *in, const vpm_replan_out *out);
+int run_replan(vpm_ctx *ctx, const vpm_params *p, const vpm_replan_in *in, vpm_replan_out *out,
+               hipStream_t stream);
+// Grow *buf to at least `bytes` (device-synchronises before freeing).
+int ensure_buffer(void **buf, size_t *have, size_t bytes, const char *what, bool capturing);
 int launch_mppi(int K, int H, const double *cost, double lambda,
                 const double *u_mean, const double *u_eps, double *w_out,
                 double *u_new, int32_t *argmin, double *jmin,

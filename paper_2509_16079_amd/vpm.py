@@ -76,6 +76,8 @@ def lib():
         L.vpm_set_tuning.argtypes = [_P, _I, _I, _I]
         L.vpm_get_tuning.argtypes = [_P, _I, C.POINTER(_I), C.POINTER(_I)]
         L.vpm_policy.argtypes = [_P, C.POINTER(PolicyIn), C.POINTER(PolicyOut), _P]
+        L.vpm_replan.argtypes = [_P, C.POINTER(Params), C.POINTER(ReplanIn),
+                                 C.POINTER(ReplanOut), _P]
         L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
         L.vpm_pair_count.restype = C.c_int64
         _lib = L
@@ -89,6 +91,20 @@ class PolicyIn(C.Structure):
 
 class PolicyOut(C.Structure):
     _fields_ = [("a", _P), ("b", _P), ("gain", _P), ("s", _P), ("status", _P)]
+
+
+class ReplanIn(C.Structure):
+    _fields_ = [("dt", _D), ("H", _I), ("P", _I), ("K", _I), ("iterations", _I), ("Kp", _I),
+                ("n_wake", _I), ("n_pairs", _I), ("reserved", _I), ("g", _P), ("gb", _P),
+                ("wx", _P), ("wz", _P), ("wg", _P), ("pairs", _P), ("u_plan", _P),
+                ("x_plan", _P), ("gain_plan", _P), ("u_eps", _P), ("x_eps", _P), ("du", _P),
+                ("lam", _D), ("x_goal", _D * 7), ("q_diag", _D * 7), ("q_f", _D * 7),
+                ("q_c", _D * 7), ("r_c", _D)]
+
+
+class ReplanOut(C.Structure):
+    _fields_ = [("g_proj", _P), ("u_new", _P), ("x_new", _P), ("gain", _P), ("jmin", _P),
+                ("argmin", _P), ("status", _P)]
 
 
 class VpmError(RuntimeError):
@@ -355,6 +371,41 @@ def policy(ctx: Context, traj_nom, traj, du, dt, q_f, q_c, r_c, want_s=True, str
                      _ptr(out["s"]) if want_s else None, _ptr(out["status"]))
     check(lib().vpm_policy(ctx.h, C.byref(pin), C.byref(pout), _stream_handle(stream)),
           "vpm_policy")
+    return out
+
+
+def replan(ctx: Context, params: dict, precision, dt, state, plan, u_eps, x_eps, du, lam,
+           x_goal, q_diag, q_f, q_c, r_c, P_steps, stream=None):
+    """One replanning cycle (vpm_replan). ``state`` = (g [7], gb [N_b], wx, wz,
+    wg, pairs [2P] or None), ``plan`` = (u_plan [H], x_plan [H, 7] or None,
+    gain_plan [H, 7] or None), u_eps [I, K, H], x_eps [Kp, 7], du [Kp, H]:
+    float64 (pairs int32) device tensors. Returns a dict of device tensors
+    g_proj, u_new, x_new, gain, jmin, argmin, status."""
+    import torch
+    g, gb, wx, wz, wg, pairs = state
+    u_plan, x_plan, gain_plan = plan
+    iters, K, H = u_eps.shape
+    Kp = x_eps.shape[0]
+    dev = u_plan.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = dict(g_proj=torch.empty(7, **f64), u_new=torch.empty(H, **f64),
+               x_new=torch.empty((H + 1, 7), **f64), gain=torch.empty((H, 7), **f64),
+               jmin=torch.empty(iters, **f64),
+               argmin=torch.empty(iters, dtype=torch.int32, device=dev),
+               status=torch.empty(H, dtype=torch.int32, device=dev))
+    n_pairs = 0 if pairs is None else pairs.numel() // 2
+    rin = ReplanIn(float(dt), H, int(P_steps), K, iters, Kp, wx.numel(), n_pairs, 0,
+                   _ptr(g), _ptr(gb), _ptr(wx), _ptr(wz), _ptr(wg), _ptr(pairs), _ptr(u_plan),
+                   _ptr(x_plan), _ptr(gain_plan), _ptr(u_eps), _ptr(x_eps), _ptr(du), float(lam))
+    for i in range(7):
+        rin.x_goal[i], rin.q_diag[i] = float(x_goal[i]), float(q_diag[i])
+        rin.q_f[i], rin.q_c[i] = float(q_f[i]), float(q_c[i])
+    rin.r_c = float(r_c)
+    rout = ReplanOut(*[_ptr(out[k]) for k in ("g_proj", "u_new", "x_new", "gain", "jmin",
+                                              "argmin", "status")])
+    p = make_params(params, precision)
+    check(lib().vpm_replan(ctx.h, C.byref(p), C.byref(rin), C.byref(rout),
+                           _stream_handle(stream)), "vpm_replan")
     return out
 
 

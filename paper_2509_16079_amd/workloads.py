@@ -193,6 +193,42 @@ def policy_batch(seed=5, K=256, H=77, dt=0.01, n_bound=32):
                     meta=dict(pair_gamma=float(gam), pair_x=float(xp), pair_zc=float(zc)))
 
 
+# Weights of the paper's controller experiments (Sec. V-A): the NMPC cost
+# and the TVLQR weights.
+Q_NMPC = np.array([10.0, 10.0, 1.0, 0.0, 0.2, 0.2, 0.2])
+TVLQR_Q_F = np.array([400.0, 400.0, 10.0, 1.0, 1.0, 1.0, 1.0])
+TVLQR_Q_C = np.array([0.1, 0.1, 5.0, 0.1, 0.1, 0.1, 5.0])
+TVLQR_R_C = 0.01
+
+
+def replan_case(seed=6, K=256, H=77, P=10, iterations=3, Kp=256, n_bound=32, dt=0.01):
+    """Inputs of one replanning cycle at the paper's controller size (MPPI
+    batch 256, 3 iterations, 77-step plan, dt = 10 ms, replanning every
+    100 ms = 10 steps): the resident state is the 7 m/s level start with one
+    disturbance pair ahead (as in the realtime batch) and no shed wake yet,
+    the plan in force is the pitch-up of policy_batch (open loop), MPPI
+    perturbations N(0, 0.15^2), policy perturbations as in policy_batch.
+    Returns a dict of numpy arrays (rounded to binary32 like every input)."""
+    rng = _rng(seed)
+    p = make_params(n_bound, n_wake_max=0)
+    gam = rng.uniform(0.2, 0.8)
+    xp = rng.uniform(1.5, 2.5)
+    zc = rng.uniform(-0.3, 0.3)
+    x, z, g = _pair(xp, zc, gam)
+    g0 = np.zeros(7)
+    g0[4] = 7.0
+    return dict(
+        params=p, dt=float(f32(dt)), H=H, P=P, K=K, iterations=iterations, Kp=Kp,
+        g=f32(g0), gb=np.zeros(n_bound), wx=f32(x), wz=f32(z), wg=f32(g),
+        pairs=np.array([0, 1], dtype=np.int32),
+        u_plan=f32(-1.5 * np.sin(np.linspace(0.0, np.pi, H))),
+        u_eps=f32(rng.normal(0.0, 0.15, size=(iterations, K, H))),
+        x_eps=f32(rng.normal(size=(Kp, 7)) * POLICY_SIGMA_X),
+        du=f32(rng.normal(0.0, POLICY_SIGMA_U, size=(Kp, H))),
+        lam=1.0, x_goal=X_GOAL.copy(), q_diag=Q_NMPC.copy(), q_f=TVLQR_Q_F.copy(),
+        q_c=TVLQR_Q_C.copy(), r_c=TVLQR_R_C)
+
+
 def random_field(rng, n, box=(0.0, 3.0, -0.5, 0.5), sigma_gamma=0.05):
     """n vortices uniform in the box with N(0, sigma^2) strengths, shifted to
     zero total circulation (the paper's flow starts at zero circulation)."""

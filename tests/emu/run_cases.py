@@ -86,11 +86,42 @@ def policy_case(ctx, name):
         flush=True)
 
 
+def replan_case(ctx):
+    """One replanning cycle (projection, MPPI iterations, policy) against the
+    cycle's oracle, then a second cycle closed by the first one's policy."""
+    import torch
+    from oracle import replan as OR
+    c = W.replan_case(K=12, H=8, P=3, iterations=2, Kp=8, n_bound=16)
+    t = lambda a: None if a is None else torch.tensor(
+        np.ascontiguousarray(a), dtype=torch.int32 if np.asarray(a).dtype == np.int32 else
+        torch.float64)
+    state = (c["g"], c["gb"], c["wx"], c["wz"], c["wg"], c["pairs"])
+    rows = {}
+    plans = [(c["u_plan"], None, None)] * 2
+    for cyc in range(2):
+        g = V.replan(ctx, c["params"], V.FP64, c["dt"], tuple(t(a) for a in state),
+                     tuple(t(a) for a in plans[0]), t(c["u_eps"]), t(c["x_eps"]), t(c["du"]),
+                     c["lam"], c["x_goal"], c["q_diag"], c["q_f"], c["q_c"], c["r_c"], c["P"],
+                     stream=_Stream())
+        g = {k: v.numpy() for k, v in g.items()}
+        o = OR.replan(c["params"], c["dt"], *state, *plans[1], c["P"], c["u_eps"], c["x_eps"],
+                      c["du"], c["lam"], c["x_goal"], c["q_diag"], c["q_f"], c["q_c"], c["r_c"])
+        rows["cycle%d" % cyc] = {
+            "argmin_equal": bool(np.array_equal(g["argmin"], o["argmin"])),
+            "status_equal": bool(np.array_equal(g["status"], o["status"])),
+            **{k: rel_l2(g[k], o[k]) for k in ("g_proj", "jmin", "u_new", "x_new", "gain")}}
+        plans = [(g["u_new"], g["x_new"][:-1], g["gain"]), (o["u_new"], o["x_new"][:-1], o["gain"])]
+    print(json.dumps({"case": "replan", "prec": V.FP64, **rows}), flush=True)
+
+
 def main(names):
     ctx = V.Context(0)
     for name in names:
         if name.startswith("policy"):
             policy_case(ctx, name)
+            continue
+        if name == "replan":
+            replan_case(ctx)
             continue
         wl = cases()[name]()
         for cls in (V.CLASS_SMALL, V.CLASS_LARGE, V.CLASS_STREAM):

@@ -156,3 +156,30 @@ def test_policy_arguments_are_checked_without_a_gpu():
     o = V.PolicyOut.from_buffer_copy(pout)
     o.gain = None
     assert L.vpm_policy(fake, C.byref(pin), C.byref(o), None) == V.EINVAL
+
+
+def test_replan_arguments_are_checked_without_a_gpu():
+    L = V.lib()
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation is host-only
+    p = V.make_params(W.make_params(16), V.FP64)
+
+    def good():
+        r = V.ReplanIn(0.01, 10, 2, 8, 2, 8, 4, 0, 0, fake, fake, fake, fake, fake, None, fake,
+                       None, None, fake, fake, fake, 1.0)
+        r.r_c = 0.01
+        return r
+    o = V.ReplanOut(*([fake] * 7))
+    assert L.vpm_replan(None, C.byref(p), C.byref(good()), C.byref(o), None) == V.EINVAL
+    bad = [("H", 0), ("P", 11), ("P", -1), ("K", 0), ("iterations", 0), ("Kp", 0),
+           ("n_wake", -1), ("n_pairs", 5), ("lam", 0.0), ("dt", float("nan")), ("u_eps", None),
+           ("x_plan", fake)]   # x_plan without gain_plan
+    for field, value in bad:
+        r = good()
+        setattr(r, field, value)
+        assert L.vpm_replan(fake, C.byref(p), C.byref(r), C.byref(o), None) == V.EINVAL, field
+    r = good()
+    r.n_pairs, r.pairs = 1, fake                     # pairs with a wake that may merge
+    p2 = V.make_params(W.make_params(16, n_wake_max=20), V.FP64)
+    assert L.vpm_replan(fake, C.byref(p2), C.byref(r), C.byref(o), None) == V.EINVAL
+    o2 = V.ReplanOut(*([fake] * 6 + [None]))
+    assert L.vpm_replan(fake, C.byref(p), C.byref(good()), C.byref(o2), None) == V.EINVAL

@@ -57,3 +57,16 @@ def test_emulated_policy_kernels_match_oracle(emu_lib, case, deficient):
     assert row["status_equal"] and row["n_rank_deficient"] == deficient, row
     for key in ("A", "B", "S", "gain"):
         assert row[key] <= 1e-9, (key, row)
+
+
+def test_emulated_replanning_cycle_matches_oracle(emu_lib):
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), "replan"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-3000:]
+    row = [json.loads(x) for x in r.stdout.splitlines() if x.startswith("{")][0]
+    for cyc in ("cycle0", "cycle1"):
+        c = row[cyc]
+        assert c["argmin_equal"] and c["status_equal"], row
+        for key in ("g_proj", "jmin", "u_new", "x_new"):
+            assert c[key] <= 1e-10, (cyc, key, row)
+        assert c["gain"] <= 1e-7, (cyc, row)
