@@ -19,6 +19,11 @@ Workloads (``--workload``):
                       perturbed FP64 rollouts of 77 steps (dt = 10 ms) and
                       the TVLQR recursion; one step = one vpm_policy call on
                       resident trajectories
+  table1              the paper's runtime-versus-batch table (Table I): batches
+                      of 1, 128, 256, 512 and 1024 rollouts of 80 steps at
+                      dt = 10 ms with at most 60 wake vortices; one step = one
+                      rollout batch + MPPI weights; the paper's RTX 5080
+                      runtimes are printed beside ours as context
   replan              one replanning cycle of the nonlinear MPC (Sec. IV-C)
                       at the paper's controller size: projection by 10 steps
                       under the policy in force, 3 MPPI iterations of 256
@@ -53,7 +58,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress", "policy",
-                                           "replan"],
+                                           "replan", "table1"],
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -535,6 +540,68 @@ def replan_main(args):
     print(json.dumps(line), flush=True)
 
 
+def table1_main(args):
+    import torch
+
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    steps = 20 if args.steps is None else args.steps
+    warmup = 3 if args.warmup is None else args.warmup
+    prec_name = args.precision or "fp32c"
+    prec = V.FP32C if prec_name == "fp32c" else V.FP64
+    ctx = V.Context(0)
+    tuning = apply_tuning(ctx, args.tuning)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for K, paper_ms in zip(W.TABLE1_BATCHES, W.TABLE1_PAPER_MS):
+        wl = W.table1(K)
+        db = V.DeviceBatch(wl)
+        out = V.DeviceOutputs(db)
+
+        def step():
+            ctx.rollout(wl.params, db, out, prec, stream)
+            ctx.mppi(out.cost, wl.lam, db.u_mean, db.u_eps, stream)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record(stream)
+            step()
+            ev[1].record(stream)
+            evs.append(ev)
+        torch.cuda.synchronize()
+        wall = 1e3 * (time.perf_counter() - t0) / steps
+        gpu = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        pairs = int(out.pair_count.sum().item())
+        rows.append({"K": K, "ms_per_step": wall, "gpu_ms": gpu, "rollouts_per_s": K / (wall * 1e-3),
+                     "pairs_per_s": pairs / (wall * 1e-3),
+                     "nonfinite_rollouts": int((out.status != 0).sum().item()),
+                     "paper_rtx5080_ms": paper_ms})
+    top = rows[-1]
+    line = {
+        "metric": "MPPI rollouts/s (the paper's runtime-versus-batch table)",
+        "value": top["rollouts_per_s"], "unit": "rollouts/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": top["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == V.FP32C else "f64", "data": "synthetic",
+        "config": {"workload": "table1: 80 steps, dt=10 ms, merging above 60 wake vortices, "
+                               "N_b=32, one disturbance pair; batch 1024 is the value",
+                   "H": 80, "n_bound": 32, "precision": prec_name},
+        "batches": rows,
+        "paper_context": "RTX 5080 runtimes of the paper's table (precision, N_b and what the "
+                         "timing includes are not stated): 8.0 / 10.3 / 12.2 / 16.3 / 27.2 ms",
+        "tuning": tuning,
+        "kernel_timing": "HIP events around each step (rollout batch + MPPI weights); "
+                         "ms_per_step is wall time per step with launches enqueued back to back",
+        "gpu_clock_after_timed_region": gpu_clock(),
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -546,6 +613,8 @@ def main():
         return policy_main(args)
     if args.workload == "replan":
         return replan_main(args)
+    if args.workload == "table1":
+        return table1_main(args)
     import torch
 
     from paper_2509_16079_amd import vpm as V

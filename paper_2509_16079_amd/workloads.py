@@ -157,6 +157,31 @@ def realtime(seed=1, K=1024, H=200):
                     meta=dict(pair_gamma=float(gam), pair_x=float(xp), pair_zc=float(zc)))
 
 
+# Runtime-versus-batch table of the paper (Sec. III-C, Table I): 80 steps at
+# dt = 10 ms, at most 60 wake particles before merging; batch sizes 1..1024.
+TABLE1_BATCHES = (1, 128, 256, 512, 1024)
+TABLE1_PAPER_MS = (8.0, 10.3, 12.2, 16.3, 27.2)   # RTX 5080, as printed
+
+
+def table1(K, seed=7, n_bound=32):
+    """The Table I configuration at batch K: H = 80, dt = 10 ms, merging
+    above 60 wake vortices, 7 m/s level start (Sec. IV-A), one disturbance
+    pair as in the realtime batch, perturbations N(0, 0.15^2). The paper does
+    not state N_b for this run; 32 bound vortices are used."""
+    rng = _rng(seed)
+    H = 80
+    p = make_params(n_bound, n_wake_max=60)
+    gam = rng.uniform(0.2, 0.8)
+    xp = rng.uniform(1.5, 2.5)
+    zc = rng.uniform(-0.3, 0.3)
+    x, z, g = _pair(xp, zc, gam)
+    wx, wz, wg = f32(x), f32(z), f32(g)
+    fo, fof, pairs = _one_field(K, wx, wz, wg, [(0, 1)], H)
+    return Workload("table1_K%d" % K, p, K, H, float(f32(0.01)), _glider0(K, 7.0),
+                    np.zeros((K, n_bound)), fo, fof, wx, wz, wg, pairs, np.zeros(H),
+                    _eps(rng, K, H, 0.15))
+
+
 # Perturbation scales of the policy rollouts (the paper tunes its
 # covariances by sweeps and does not print them): positions 1 cm, angles
 # 0.01 rad, velocities 0.05 m/s, pitch rate 0.05 rad/s; controls 0.15.

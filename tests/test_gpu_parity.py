@@ -274,3 +274,13 @@ def test_mppi_matches_oracle(ctx):
     w, un, am, jm = ctx.mppi(t(cost), 1.0, t(mu), t(np.ones((2, 2))))
     assert int(am.item()) == -1 and np.all(w.cpu().numpy() == 0)
     assert np.array_equal(un.cpu().numpy(), mu)
+
+
+@pytest.mark.parametrize("prec", [V.FP32C, V.FP64])
+def test_table1_configuration_full_horizon(ctx, prec):
+    """The paper's runtime-table configuration (80 steps, dt = 10 ms, merging
+    above 60 vortices) at its full horizon: well conditioned (the oracle's
+    reverse-order gap is 5e-15, binary32 storage drifts 1e-6), so both bars
+    hold over all 80 steps."""
+    wl = W.table1(16)
+    _horizon_parity(ctx, wl, prec)
