@@ -159,3 +159,60 @@ def test_p19_cost_to_go_matrices_are_symmetric_positive_definite(k):
     S, _ = P.tvlqr(np.array(As), np.array(Bs), P.Q_F, P.Q_C, P.R_C)
     np.testing.assert_allclose(S[k], S[k].T, rtol=0, atol=1e-12 * np.abs(S[k]).max())
     assert np.linalg.eigvalsh(S[k]).min() > 0
+
+
+# ---------------------- P21 finite-difference Jacobians through the model
+
+def _fd_case(**over):
+    from paper_2509_16079_amd import workloads as W
+    c = W.replan_case(K=8, H=10, P=0, iterations=1, Kp=8, n_bound=16)
+    c["params"] = dict(c["params"], **over)
+    return c
+
+
+def test_p21_fd_nominal_is_the_uninterrupted_rollout():
+    from oracle import fd as F
+    from oracle import oracle as O
+    c = _fd_case()
+    A, B, x_nom = F.fd_jacobians(c["params"], c["dt"], c["g"], c["gb"], c["wx"], c["wz"], c["wg"],
+                                 c["pairs"], c["u_plan"][:10], [1e-4] * 5, 1e-4)
+    ref = O.rollout_batch(c["params"], 1, 10, c["dt"], c["g"][None], c["gb"][None],
+                          np.array([0, 2], dtype=np.int64), None, c["wx"], c["wz"], c["wg"],
+                          c["pairs"][None], c["u_plan"][None, :10], np.zeros(7), np.zeros(7),
+                          traj=True)
+    np.testing.assert_allclose(x_nom, ref["traj"][0], rtol=1e-12, atol=1e-14)
+
+
+def test_p21_no_elevator_area_means_no_control_derivative():
+    # u enters the accelerations only through the elevator force
+    from oracle import fd as F
+    c = _fd_case(s_elev=0.0)
+    _, B, _ = F.fd_jacobians(c["params"], c["dt"], c["g"], c["gb"], c["wx"], c["wz"], c["wg"],
+                             c["pairs"], c["u_plan"][:10], [1e-4] * 5, 1e-4)
+    assert np.all(B[:, 4:7] == 0.0)
+    assert np.all(B[:, 3] == c["dt"])
+
+
+def test_p21_first_step_agrees_with_the_least_squares_synthesis():
+    # at step 0 both methods perturb the same state and wake: with 1e-6
+    # perturbations of the regressors only (x and z are not regressors, and
+    # the wake makes the accelerations depend on them) the regression and
+    # the central differences agree to O(h)
+    from oracle import fd as F
+    from oracle import oracle as O
+    c = _fd_case()
+    A, B, _ = F.fd_jacobians(c["params"], c["dt"], c["g"], c["gb"], c["wx"], c["wz"], c["wg"],
+                             c["pairs"], c["u_plan"][:1], [1e-6] * 5, 1e-6)
+    rng = np.random.default_rng(0)
+    K = 64
+    g0 = np.repeat(c["g"][None], K + 1, 0)
+    g0[1:, 2:] += rng.normal(scale=1e-6, size=(K, 5))
+    du = np.zeros((K + 1, 1))
+    du[1:, 0] = rng.normal(scale=1e-6, size=K)
+    tr = O.rollout_batch(c["params"], K + 1, 1, c["dt"], g0, np.zeros((K + 1, 16)),
+                         np.array([0, 2], dtype=np.int64), np.zeros(K + 1, dtype=np.int32),
+                         c["wx"], c["wz"], c["wg"], None, c["u_plan"][None, :1] + du,
+                         np.zeros(7), np.zeros(7), traj=True)["traj"]
+    syn = P.synthesize(tr[0], tr[1:], du[1:], c["dt"])
+    np.testing.assert_allclose(syn["A"][0], A[0], rtol=0, atol=1e-4 * np.abs(A[0]).max())
+    np.testing.assert_allclose(syn["B"][0], B[0], rtol=0, atol=1e-4 * np.abs(B[0]).max())
