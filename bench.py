@@ -24,6 +24,12 @@ Workloads (``--workload``):
                       dt = 10 ms with at most 60 wake vortices; one step = one
                       rollout batch + MPPI weights; the paper's RTX 5080
                       runtimes are printed beside ours as context
+  icsweep             the comparison of Sec. IV-B's Fig. 3: open loop,
+                      least-squares and finite-difference TVLQR feedback
+                      from 41 initial forward speeds offset by -0.5..0.5 m/s
+                      around the nominal of one replanning cycle; reports
+                      each policy's region of attraction (5 cm final
+                      position error) and the time of the whole pipeline
   replan              one replanning cycle of the nonlinear MPC (Sec. IV-C)
                       at the paper's controller size: projection by 10 steps
                       under the policy in force, 3 MPPI iterations of 256
@@ -58,7 +64,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress", "policy",
-                                           "replan", "table1"],
+                                           "replan", "table1", "icsweep"],
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -602,6 +608,63 @@ def table1_main(args):
     print(json.dumps(line), flush=True)
 
 
+def icsweep_main(args):
+    import torch
+
+    from paper_2509_16079_amd import icsweep as S
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    steps = 3 if args.steps is None else args.steps
+    prec_name = args.precision or "fp64"
+    prec = V.FP32C if prec_name == "fp32c" else V.FP64
+    c = W.replan_case(P=0)
+    offsets = np.linspace(-0.5, 0.5, 41)
+    ctx = V.Context(0)
+    tuning = apply_tuning(ctx, args.tuning)
+    g = S.run(ctx, c, offsets, prec)        # warm-up (builds inverses, workspaces)
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = S.run(ctx, c, offsets, prec)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+    roa = {k: g[k]["roa"] for k in ("open", "ls", "fd")}
+    width = {k: (v[1] - v[0]) if v else 0.0 for k, v in roa.items()}
+    line = {
+        "metric": "initial-condition sweep: region of attraction per policy (5 cm final "
+                  "position error) and pipeline time",
+        "value": float(np.median(times)), "unit": "ms", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": float(np.median(times)), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == V.FP64 else "f32", "data": "synthetic",
+        "config": {"workload": "icsweep: replanning cycle (3 x 256 MPPI rollouts, 77 steps, "
+                               "257 policy rollouts), FD Jacobians along its nominal, 3 x 41 "
+                               "sweep rollouts over x_dot offsets -0.5..0.5 m/s",
+                   "precision": prec_name},
+        "region_of_attraction_m_per_s": roa,
+        "roa_width_m_per_s": width,
+        "final_pos_err_m": {k: [round(float(x), 4) for x in g[k]["pos_err"]]
+                            for k in ("open", "ls", "fd")},
+        "offsets_m_per_s": [round(float(x), 4) for x in offsets],
+        "tuning": tuning,
+        "kernel_timing": "wall time of the whole pipeline (every stage synchronised)",
+    }
+    if not args.no_cpu_baseline:
+        from oracle import icsweep as OI
+        t0 = time.perf_counter()
+        o = OI.run(c, offsets, S.FD_H_X, S.FD_H_U)
+        line["cpu_baseline"] = {"value": 1e3 * (time.perf_counter() - t0), "unit": "ms",
+                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+                                "kind": "oracle", "sample": "the whole sweep (FP64)"}
+        line["error_vs_oracle"] = {
+            k: {"g_final_rel_l2": _rel_l2(g[k]["g_final"], o[k]["g_final"]),
+                "roa_equal": S.region_of_attraction(offsets, o[k]["pos_err"]) == g[k]["roa"]}
+            for k in ("open", "ls", "fd")}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -615,6 +678,8 @@ def main():
         return replan_main(args)
     if args.workload == "table1":
         return table1_main(args)
+    if args.workload == "icsweep":
+        return icsweep_main(args)
     import torch
 
     from paper_2509_16079_amd import vpm as V

@@ -451,6 +451,52 @@ typedef struct {
 VPM_API int vpm_replan(vpm_ctx *ctx, const vpm_params *params, const vpm_replan_in *in,
                        vpm_replan_out *out, void *stream);
 
+/* TVLQR alone (Eqs. 29-30 as in vpm_policy) on caller-supplied discrete
+ * systems: a [H][7][7] (row-major) and b [H][7] in, gain [H][7] and
+ * optionally s [H+1][7][7] out, all device memory. Serves policies whose
+ * Jacobians come from elsewhere, such as the finite-difference ones below.
+ * Errors: VPM_EINVAL, VPM_EDEVICE. */
+VPM_API int vpm_tvlqr(vpm_ctx *ctx, int32_t H, const double *a, const double *b,
+                      const double q_f[7], const double q_c[7], double r_c, double *gain,
+                      double *s, void *stream);
+
+/* Finite-difference Jacobians through the model (the alternative to the
+ * least-squares synthesis that Sec. IV-B compares against): along the
+ * nominal trajectory from the given state under controls u_nom, at every
+ * step k the one-step accelerations (x_{k+1} - x_k)/dt of rows x_dot,
+ * z_dot, theta_dot are differenced centrally in theta, phi, x_dot, z_dot,
+ * theta_dot (steps h_x) and in u (step h_u), each perturbed one-step
+ * rollout starting from the nominal's full state at step k (glider, bound
+ * circulations, wake). The result has the form of vpm_policy's: A_k =
+ * I + dt A_c, B_k = dt B_c with the kinematic rows known. FP64 rollouts;
+ * the nominal is advanced one step at a time (2 launches per step).
+ * Disturbance pairs follow vpm_replan's rule. Errors: VPM_EINVAL,
+ * VPM_ENOMEM, VPM_ESINGULAR, VPM_EDEVICE. */
+typedef struct {
+  double dt;
+  int32_t H;              /* steps (>= 1)                                    */
+  int32_t n_wake;         /* wake vortices of the start state (>= 0)         */
+  int32_t n_pairs;        /* disturbance pairs (0..4)                        */
+  int32_t reserved;
+  const double *g;        /* device [7] start state                          */
+  const double *gb;       /* device [N_b] its previous bound circulations    */
+  const double *wx, *wz, *wg; /* device [n_wake] start wake                  */
+  const int32_t *pairs;   /* device [2 n_pairs] or NULL                      */
+  const double *u_nom;    /* device [H] nominal controls                     */
+  double h_x[5];          /* host: steps in theta, phi, x_dot, z_dot,
+                             theta_dot (> 0)                                 */
+  double h_u;             /* host: step in u (> 0)                           */
+} vpm_fd_in;
+
+typedef struct {
+  double *a;              /* device [H][7][7]                                */
+  double *b;              /* device [H][7]                                   */
+  double *x_nom;          /* device [H+1][7] nominal trajectory, or NULL     */
+} vpm_fd_out;
+
+VPM_API int vpm_fd_jacobians(vpm_ctx *ctx, const vpm_params *params, const vpm_fd_in *in,
+                             vpm_fd_out *out, void *stream);
+
 /* Exact pair-interaction count of one rollout (host arithmetic): per step
  * N_w (2 N_b + 1) surface pairs, N_w' (N_w' - 1) wake pairs and N_w' N_b
  * bound pairs with N_w' = N_w + 2 (both edges shed), merging above

@@ -149,6 +149,7 @@ VPM_API void vpm_destroy(vpm_ctx *ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->plan) (void)hipFree(ctx->plan);
   if (ctx->replan) (void)hipFree(ctx->replan);
+  if (ctx->fd) (void)hipFree(ctx->fd);
   if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
   if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
   for (int i = 0; i < 3; ++i) {
@@ -279,6 +280,29 @@ VPM_API int vpm_replan(vpm_ctx *ctx, const vpm_params *params, const vpm_replan_
   if (rc == VPM_OK) rc = vpm::check_replan(params, in, out);
   if (rc != VPM_OK) return rc;
   return vpm::run_replan(ctx, params, in, out, static_cast<hipStream_t>(stream));
+}
+
+VPM_API int vpm_tvlqr(vpm_ctx *ctx, int32_t H, const double *a, const double *b,
+                      const double q_f[7], const double q_c[7], double r_c, double *gain,
+                      double *s, void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  if (H < 1) return fail(VPM_EINVAL, "H must be >= 1");
+  if (!a || !b || !gain || !q_f || !q_c) return fail(VPM_EINVAL, "a pointer is NULL");
+  if (!vpm::finite_pos(r_c)) return fail(VPM_EINVAL, "r_c must be > 0");
+  for (int i = 0; i < 7; ++i)
+    if (!(std::isfinite(q_f[i]) && q_f[i] >= 0.0 && std::isfinite(q_c[i]) && q_c[i] >= 0.0))
+      return fail(VPM_EINVAL, "q_f and q_c must be finite and >= 0");
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  return vpm::launch_tvlqr(H, a, b, q_f, q_c, r_c, gain, s, static_cast<hipStream_t>(stream));
+}
+
+VPM_API int vpm_fd_jacobians(vpm_ctx *ctx, const vpm_params *params, const vpm_fd_in *in,
+                             vpm_fd_out *out, void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  int rc = vpm::check_params(params);
+  if (rc == VPM_OK) rc = vpm::check_fd(params, in, out);
+  if (rc != VPM_OK) return rc;
+  return vpm::run_fd(ctx, params, in, out, static_cast<hipStream_t>(stream));
 }
 
 VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,

@@ -255,4 +255,22 @@ int launch_policy(const vpm_policy_in *in, vpm_policy_out *out, hipStream_t stre
   return VPM_OK;
 }
 
+int launch_tvlqr(int H, const double *a, const double *b, const double *q_f, const double *q_c,
+                 double r_c, double *gain, double *s, hipStream_t stream) {
+  PolicyArgs p{};
+  p.H = H;
+  for (int i = 0; i < kNx; ++i) {
+    p.q_f[i] = q_f[i];
+    p.q_c[i] = q_c[i];
+  }
+  p.r_c = r_c;
+  p.a = const_cast<double *>(a);  // the recursion only reads A and B
+  p.b = const_cast<double *>(b);
+  p.gain = gain;
+  p.s = s;
+  hipLaunchKernelGGL(riccati_kernel, dim3(1), dim3(64), 0, stream, p);
+  VPM_HIP_TRY(hipGetLastError());
+  return VPM_OK;
+}
+
 }  // namespace vpm

@@ -332,3 +332,225 @@ int run_replan(vpm_ctx *ctx, const vpm_params *p, const vpm_replan_in *in, vpm_r
 }
 
 }  // namespace vpm
+
+// ------------------------------------------- finite-difference Jacobians
+
+namespace vpm {
+namespace {
+
+constexpr int kFdRows = 13;  // nominal, +-h for 5 states, +-h for u
+
+struct FdSteps {
+  double hx[5], hu;
+};
+
+// The 13 one-step rollouts of step k from the current nominal state: row 0
+// unperturbed, rows 1 + 2j / 2 + 2j with +h_j / -h_j on state 2 + j
+// (theta, phi, x_dot, z_dot, theta_dot), rows 11 / 12 with +h_u / -h_u on u.
+__global__ void fd_inputs_kernel(const double *g_cur, const double *gb_cur, const int32_t *n_cur,
+                                 FdSteps h, const int32_t *pairs, int n_pairs, int nb,
+                                 double *g0, double *gb0, double *u_eps, int32_t *pairs_out,
+                                 int64_t *field_off, int32_t *field_of) {
+  const int i = blockIdx.x, t = threadIdx.x;
+  if (i == 0 && t == 0) {
+    field_off[0] = 0;
+    field_off[1] = n_cur[0];
+  }
+  if (t < 7) {
+    double v = g_cur[t];
+    if (i >= 1 && i <= 10 && t == 2 + (i - 1) / 2) v += (i % 2 == 1 ? 1.0 : -1.0) * h.hx[(i - 1) / 2];
+    g0[i * 7 + t] = v;
+  }
+  for (int j = t; j < nb; j += blockDim.x) gb0[(size_t)i * nb + j] = gb_cur[j];
+  if (t == 0) {
+    u_eps[i] = i == 11 ? h.hu : i == 12 ? -h.hu : 0.0;
+    field_of[i] = 0;
+  }
+  if (t < 2 * n_pairs) pairs_out[(size_t)i * 2 * n_pairs + t] = pairs[t];
+}
+
+// Central differences of the one-step accelerations (x_{k+1} - x_k)/dt of
+// rows x_dot, z_dot, theta_dot, and the explicit Euler map of Eq. 28's form.
+__global__ void fd_jacobian_kernel(const double *g0, const double *g1, double dt, FdSteps h,
+                                   double *A, double *B, double *x_nom) {
+  if (threadIdx.x != 0) return;
+  auto acc = [&](int i, int r) { return (g1[i * 7 + 4 + r] - g0[i * 7 + 4 + r]) / dt; };
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) A[r * 7 + c] = r == c ? 1.0 : 0.0;
+  A[0 * 7 + 4] = A[1 * 7 + 5] = A[2 * 7 + 6] = dt;
+  for (int r = 0; r < 7; ++r) B[r] = 0.0;
+  B[3] = dt;
+  for (int r = 0; r < 3; ++r) {
+    for (int j = 0; j < 5; ++j)
+      A[(4 + r) * 7 + 2 + j] += dt * (acc(1 + 2 * j, r) - acc(2 + 2 * j, r)) / (2.0 * h.hx[j]);
+    B[4 + r] = dt * (acc(11, r) - acc(12, r)) / (2.0 * h.hu);
+  }
+  if (x_nom)
+    for (int c = 0; c < 7; ++c) x_nom[c] = g0[c];
+}
+
+// Start state into the first of the two state buffers; field offsets of the
+// wake output layout.
+__global__ void fd_init_kernel(int32_t *n_cur, int n_wake, int64_t *wake_off, int64_t cap) {
+  if (threadIdx.x == 0) {
+    n_cur[0] = n_wake;
+    wake_off[0] = 0;
+    wake_off[1] = cap;
+  }
+}
+
+struct FdLayout {
+  double *g[2], *gb[2], *wx[2], *wz[2], *wg[2];
+  int32_t *n[2];
+  int64_t *wake_off, *field_off;
+  double *g0, *gb0, *u_eps, *g1, *cost, *zero, *cost1;
+  int32_t *status, *status1, *pairs, *field_of;
+  size_t bytes;
+};
+
+FdLayout fd_layout(char *base, const vpm_fd_in *in, int nb) {
+  Arena ar{base, 0};
+  FdLayout L{};
+  const size_t cap = (size_t)in->n_wake + 2 * (size_t)in->H + 2;
+  for (int s = 0; s < 2; ++s) {
+    L.g[s] = ar.take<double>(7);
+    L.gb[s] = ar.take<double>(nb);
+    L.wx[s] = ar.take<double>(cap);
+    L.wz[s] = ar.take<double>(cap);
+    L.wg[s] = ar.take<double>(cap);
+    L.n[s] = ar.take<int32_t>(1);
+  }
+  L.wake_off = ar.take<int64_t>(2);
+  L.field_off = ar.take<int64_t>(2);
+  L.g0 = ar.take<double>(kFdRows * 7);
+  L.gb0 = ar.take<double>((size_t)kFdRows * nb);
+  L.u_eps = ar.take<double>(kFdRows);
+  L.g1 = ar.take<double>(kFdRows * 7);
+  L.cost = ar.take<double>(kFdRows);
+  L.zero = ar.take<double>(1);
+  L.cost1 = ar.take<double>(1);
+  L.status = ar.take<int32_t>(kFdRows);
+  L.status1 = ar.take<int32_t>(1);
+  L.pairs = ar.take<int32_t>((size_t)kFdRows * 2 * (in->n_pairs > 0 ? in->n_pairs : 1));
+  L.field_of = ar.take<int32_t>(kFdRows);
+  L.bytes = ar.off + 256;
+  return L;
+}
+
+}  // namespace
+
+int check_fd(const vpm_params *p, const vpm_fd_in *in, const vpm_fd_out *out) {
+  if (!p || !in || !out) return fail(VPM_EINVAL, "params, in or out is NULL");
+  if (!(std::isfinite(in->dt) && in->dt > 0.0)) return fail(VPM_EINVAL, "dt must be > 0");
+  if (in->H < 1) return fail(VPM_EINVAL, "H must be >= 1");
+  if (in->n_wake < 0) return fail(VPM_EINVAL, "n_wake must be >= 0");
+  if (in->n_pairs < 0 || in->n_pairs > kMaxPairs) return fail(VPM_EINVAL, "n_pairs must be 0..4");
+  if (in->n_pairs > 0) {
+    if (!in->pairs) return fail(VPM_EINVAL, "pairs is NULL with n_pairs > 0");
+    if (p->n_wake_max > 0 && (long long)in->n_wake + 2LL * in->H > p->n_wake_max)
+      return fail(VPM_EINVAL, "disturbance pairs need a wake that cannot merge within H steps");
+  }
+  for (double h : in->h_x)
+    if (!(std::isfinite(h) && h > 0.0)) return fail(VPM_EINVAL, "h_x must be > 0");
+  if (!(std::isfinite(in->h_u) && in->h_u > 0.0)) return fail(VPM_EINVAL, "h_u must be > 0");
+  if (!in->g || !in->gb || !in->u_nom) return fail(VPM_EINVAL, "a required input pointer is NULL");
+  if (in->n_wake > 0 && (!in->wx || !in->wz || !in->wg))
+    return fail(VPM_EINVAL, "wake pointers are NULL");
+  if (!out->a || !out->b) return fail(VPM_EINVAL, "a required output pointer is NULL");
+  return VPM_OK;
+}
+
+int run_fd(vpm_ctx *ctx, const vpm_params *p, const vpm_fd_in *in, vpm_fd_out *out,
+           hipStream_t stream) {
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  const int nb = p->n_bound, H = in->H;
+  std::lock_guard<std::mutex> lock(ctx->replan_mu);
+  FdLayout L = fd_layout(nullptr, in, nb);
+  int rc = ensure_buffer(&ctx->fd, &ctx->fd_bytes, L.bytes, "finite-difference workspace",
+                         stream_capturing(stream));
+  if (rc != VPM_OK) return rc;
+  L = fd_layout(static_cast<char *>(ctx->fd), in, nb);
+  vpm_params p64 = *p;
+  p64.precision = VPM_FP64;
+  void *sv = stream;
+  const int64_t cap = (int64_t)in->n_wake + 2 * (int64_t)H + 2;
+  FdSteps h{};
+  for (int j = 0; j < 5; ++j) h.hx[j] = in->h_x[j];
+  h.hu = in->h_u;
+  // the start state into buffer 0
+  hipLaunchKernelGGL(fd_init_kernel, dim3(1), dim3(64), 0, stream, L.n[0], in->n_wake, L.wake_off,
+                     cap);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kFill), 0, stream, L.zero, (size_t)1, 0.0);
+  VPM_HIP_TRY(hipMemcpyAsync(L.g[0], in->g, 7 * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  VPM_HIP_TRY(hipMemcpyAsync(L.gb[0], in->gb, nb * sizeof(double), hipMemcpyDeviceToDevice,
+                             stream));
+  if (in->n_wake > 0) {
+    const size_t nw = (size_t)in->n_wake * sizeof(double);
+    VPM_HIP_TRY(hipMemcpyAsync(L.wx[0], in->wx, nw, hipMemcpyDeviceToDevice, stream));
+    VPM_HIP_TRY(hipMemcpyAsync(L.wz[0], in->wz, nw, hipMemcpyDeviceToDevice, stream));
+    VPM_HIP_TRY(hipMemcpyAsync(L.wg[0], in->wg, nw, hipMemcpyDeviceToDevice, stream));
+  }
+  auto batch = [&](int cur, int K, const double *g0, const double *gb0, const double *u_mean,
+                   const double *u_eps, int max_wake0) {
+    vpm_batch_in b{};
+    b.K = K;
+    b.H = 1;
+    b.dt = in->dt;
+    b.n_fields = 1;
+    b.max_wake0 = max_wake0;
+    b.n_pairs = in->n_pairs;
+    b.g0 = g0;
+    b.gb0 = gb0;
+    b.field_off = L.field_off;
+    b.field_of = L.field_of;
+    b.wx = L.wx[cur];
+    b.wz = L.wz[cur];
+    b.wg = L.wg[cur];
+    b.pairs = in->n_pairs > 0 ? L.pairs : nullptr;
+    b.u_mean = u_mean;
+    b.u_eps = u_eps;
+    for (int i = 0; i < 7; ++i) b.q_diag[i] = 0.0;
+    return b;
+  };
+  int cur = 0;
+  for (int k = 0; k < H; ++k) {
+    const int max_wake0 = in->n_wake + 2 * k;
+    hipLaunchKernelGGL(fd_inputs_kernel, dim3(kFdRows), dim3(64), 0, stream, L.g[cur], L.gb[cur],
+                       L.n[cur], h, in->pairs, in->n_pairs, nb, L.g0, L.gb0, L.u_eps, L.pairs,
+                       L.field_off, L.field_of);
+    VPM_HIP_TRY(hipGetLastError());
+    // the 13 perturbed one-step rollouts, then their differences
+    vpm_batch_in b = batch(cur, kFdRows, L.g0, L.gb0, in->u_nom + k, L.u_eps, max_wake0);
+    vpm_batch_out o{};
+    o.g_final = L.g1;
+    o.cost = L.cost;
+    o.status = L.status;
+    rc = vpm_rollout_batch(ctx, &p64, &b, &o, sv);
+    if (rc != VPM_OK) return rc;
+    hipLaunchKernelGGL(fd_jacobian_kernel, dim3(1), dim3(64), 0, stream, L.g0, L.g1, in->dt, h,
+                       out->a + (size_t)k * 49, out->b + (size_t)k * 7,
+                       out->x_nom ? out->x_nom + (size_t)k * 7 : nullptr);
+    VPM_HIP_TRY(hipGetLastError());
+    // advance the nominal one step (same inputs as row 0) into the other buffer
+    vpm_batch_in bn = batch(cur, 1, L.g[cur], L.gb[cur], in->u_nom + k, L.zero, max_wake0);
+    vpm_batch_out on{};
+    on.g_final = L.g[1 - cur];
+    on.cost = L.cost1;
+    on.status = L.status1;
+    on.wake_off = L.wake_off;
+    on.wx = L.wx[1 - cur];
+    on.wz = L.wz[1 - cur];
+    on.wg = L.wg[1 - cur];
+    on.n_final = L.n[1 - cur];
+    on.gb_final = L.gb[1 - cur];
+    rc = vpm_rollout_batch(ctx, &p64, &bn, &on, sv);
+    if (rc != VPM_OK) return rc;
+    cur = 1 - cur;
+  }
+  if (out->x_nom)
+    VPM_HIP_TRY(hipMemcpyAsync(out->x_nom + (size_t)H * 7, L.g[cur], 7 * sizeof(double),
+                               hipMemcpyDeviceToDevice, stream));
+  return VPM_OK;
+}
+
+}  // namespace vpm

@@ -83,10 +83,12 @@ struct vpm_ctx {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t fork_event = nullptr;
   hipEvent_t join_event[3] = {nullptr, nullptr, nullptr};
-  // replanning-cycle workspace (vpm_replan), grown on demand
+  // replanning-cycle and finite-difference workspaces, grown on demand
   std::mutex replan_mu;
   void *replan = nullptr;
   size_t replan_bytes = 0;
+  void *fd = nullptr;
+  size_t fd_bytes = 0;
 };
 
 namespace vpm {
@@ -118,6 +120,12 @@ int launch_plate_solve(const vpm_params *p, int B, const double *pose,
                        const double *kinv_t, double *gamma_s,
                        hipStream_t stream);
 int launch_policy(const vpm_policy_in *in, vpm_policy_out *out, hipStream_t stream);
+int launch_tvlqr(int H, const double *a, const double *b, const double *q_f, const double *q_c,
+                 double r_c, double *gain, double *s, hipStream_t stream);
+// Host-only argument checks (no device access) and drivers of vpm_fd_jacobians.
+int check_fd(const vpm_params *p, const vpm_fd_in *in, const vpm_fd_out *out);
+int run_fd(vpm_ctx *ctx, const vpm_params *p, const vpm_fd_in *in, vpm_fd_out *out,
+           hipStream_t stream);
 // Host-only argument check of vpm_replan (no device access).
 int check_replan(const vpm_params *p, const vpm_replan_in *in, const vpm_replan_out *out);
 int run_replan(vpm_ctx *ctx, const vpm_params *p, const vpm_replan_in *in, vpm_replan_out *out,

@@ -78,6 +78,9 @@ def lib():
         L.vpm_policy.argtypes = [_P, C.POINTER(PolicyIn), C.POINTER(PolicyOut), _P]
         L.vpm_replan.argtypes = [_P, C.POINTER(Params), C.POINTER(ReplanIn),
                                  C.POINTER(ReplanOut), _P]
+        L.vpm_tvlqr.argtypes = [_P, _I, _P, _P, _D * 7, _D * 7, _D, _P, _P, _P]
+        L.vpm_fd_jacobians.argtypes = [_P, C.POINTER(Params), C.POINTER(FdIn), C.POINTER(FdOut),
+                                       _P]
         L.vpm_pair_count.argtypes = [_I, _I, _I, _I]
         L.vpm_pair_count.restype = C.c_int64
         _lib = L
@@ -105,6 +108,16 @@ class ReplanIn(C.Structure):
 class ReplanOut(C.Structure):
     _fields_ = [("g_proj", _P), ("u_new", _P), ("x_new", _P), ("gain", _P), ("jmin", _P),
                 ("argmin", _P), ("status", _P)]
+
+
+class FdIn(C.Structure):
+    _fields_ = [("dt", _D), ("H", _I), ("n_wake", _I), ("n_pairs", _I), ("reserved", _I),
+                ("g", _P), ("gb", _P), ("wx", _P), ("wz", _P), ("wg", _P), ("pairs", _P),
+                ("u_nom", _P), ("h_x", _D * 5), ("h_u", _D)]
+
+
+class FdOut(C.Structure):
+    _fields_ = [("a", _P), ("b", _P), ("x_nom", _P)]
 
 
 class VpmError(RuntimeError):
@@ -406,6 +419,40 @@ def replan(ctx: Context, params: dict, precision, dt, state, plan, u_eps, x_eps,
     p = make_params(params, precision)
     check(lib().vpm_replan(ctx.h, C.byref(p), C.byref(rin), C.byref(rout),
                            _stream_handle(stream)), "vpm_replan")
+    return out
+
+
+def tvlqr(ctx: Context, a, b, q_f, q_c, r_c, want_s=True, stream=None):
+    """TVLQR on given systems a [H, 7, 7], b [H, 7] (float64 device tensors,
+    vpm_tvlqr). Returns (gain [H, 7], S [H + 1, 7, 7] or None)."""
+    import torch
+    H = a.shape[0]
+    gain = torch.empty((H, 7), dtype=torch.float64, device=a.device)
+    S = torch.empty((H + 1, 7, 7), dtype=torch.float64, device=a.device) if want_s else None
+    check(lib().vpm_tvlqr(ctx.h, H, _ptr(a), _ptr(b), (_D * 7)(*map(float, q_f)),
+                          (_D * 7)(*map(float, q_c)), float(r_c), _ptr(gain), _ptr(S),
+                          _stream_handle(stream)), "vpm_tvlqr")
+    return gain, S
+
+
+def fd_jacobians(ctx: Context, params: dict, dt, state, u_nom, h_x, h_u, stream=None):
+    """Finite-difference Jacobians along the nominal (vpm_fd_jacobians).
+    state = (g [7], gb [N_b], wx, wz, wg, pairs or None) as float64 (int32)
+    device tensors. Returns dict a [H, 7, 7], b [H, 7], x_nom [H + 1, 7]."""
+    import torch
+    g, gb, wx, wz, wg, pairs = state
+    H = u_nom.shape[0]
+    dev = u_nom.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = dict(a=torch.empty((H, 7, 7), **f64), b=torch.empty((H, 7), **f64),
+               x_nom=torch.empty((H + 1, 7), **f64))
+    n_pairs = 0 if pairs is None else pairs.numel() // 2
+    fin = FdIn(float(dt), H, wx.numel(), n_pairs, 0, _ptr(g), _ptr(gb), _ptr(wx), _ptr(wz),
+               _ptr(wg), _ptr(pairs), _ptr(u_nom), (_D * 5)(*map(float, h_x)), float(h_u))
+    fout = FdOut(_ptr(out["a"]), _ptr(out["b"]), _ptr(out["x_nom"]))
+    p = make_params(params, FP64)
+    check(lib().vpm_fd_jacobians(ctx.h, C.byref(p), C.byref(fin), C.byref(fout),
+                                 _stream_handle(stream)), "vpm_fd_jacobians")
     return out
 
 

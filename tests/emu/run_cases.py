@@ -114,9 +114,33 @@ def replan_case(ctx):
     print(json.dumps({"case": "replan", "prec": V.FP64, **rows}), flush=True)
 
 
+def fd_case(ctx):
+    """Finite-difference Jacobians and TVLQR on them against the oracles."""
+    import torch
+    from oracle import fd as F
+    from oracle import policy as P
+    c = W.replan_case(K=8, H=5, P=0, iterations=1, Kp=8, n_bound=16)
+    t = lambda a: None if a is None else torch.tensor(
+        np.ascontiguousarray(a), dtype=torch.int32 if np.asarray(a).dtype == np.int32 else
+        torch.float64)
+    state = (c["g"], c["gb"], c["wx"], c["wz"], c["wg"], c["pairs"])
+    hx, hu = [1e-4] * 5, 1e-4
+    g = V.fd_jacobians(ctx, c["params"], c["dt"], tuple(t(a) for a in state), t(c["u_plan"][:5]),
+                       hx, hu, stream=_Stream())
+    gain, _ = V.tvlqr(ctx, g["a"], g["b"], P.Q_F, P.Q_C, P.R_C, stream=_Stream())
+    A, B, x_nom = F.fd_jacobians(c["params"], c["dt"], *state, c["u_plan"][:5], hx, hu)
+    _, go = P.tvlqr(A, B, P.Q_F, P.Q_C, P.R_C)
+    print(json.dumps({"case": "fd", "prec": V.FP64, "A": rel_l2(g["a"].numpy(), A),
+                      "B": rel_l2(g["b"].numpy(), B), "x_nom": rel_l2(g["x_nom"].numpy(), x_nom),
+                      "gain": rel_l2(gain.numpy(), go)}), flush=True)
+
+
 def main(names):
     ctx = V.Context(0)
     for name in names:
+        if name == "fd":
+            fd_case(ctx)
+            continue
         if name.startswith("policy"):
             policy_case(ctx, name)
             continue

@@ -183,3 +183,29 @@ def test_replan_arguments_are_checked_without_a_gpu():
     assert L.vpm_replan(fake, C.byref(p2), C.byref(r), C.byref(o), None) == V.EINVAL
     o2 = V.ReplanOut(*([fake] * 6 + [None]))
     assert L.vpm_replan(fake, C.byref(p), C.byref(good()), C.byref(o2), None) == V.EINVAL
+
+
+def test_tvlqr_and_fd_arguments_are_checked_without_a_gpu():
+    L = V.lib()
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation is host-only
+    q = (C.c_double * 7)(*([1.0] * 7))
+    assert L.vpm_tvlqr(None, 5, fake, fake, q, q, 0.01, fake, None, None) == V.EINVAL
+    assert L.vpm_tvlqr(fake, 0, fake, fake, q, q, 0.01, fake, None, None) == V.EINVAL
+    assert L.vpm_tvlqr(fake, 5, fake, fake, q, q, 0.0, fake, None, None) == V.EINVAL
+    assert L.vpm_tvlqr(fake, 5, None, fake, q, q, 0.01, fake, None, None) == V.EINVAL
+    p = V.make_params(W.make_params(16), V.FP64)
+
+    def good():
+        return V.FdIn(0.01, 10, 4, 0, 0, fake, fake, fake, fake, fake, None, fake,
+                      (C.c_double * 5)(*([1e-4] * 5)), 1e-4)
+    o = V.FdOut(fake, fake, None)
+    for field, value in [("H", 0), ("n_wake", -1), ("n_pairs", 5), ("h_u", 0.0),
+                         ("dt", 0.0), ("u_nom", None)]:
+        r = good()
+        setattr(r, field, value)
+        assert L.vpm_fd_jacobians(fake, C.byref(p), C.byref(r), C.byref(o), None) == V.EINVAL
+    r = good()
+    r.h_x[2] = -1e-4
+    assert L.vpm_fd_jacobians(fake, C.byref(p), C.byref(r), C.byref(o), None) == V.EINVAL
+    assert L.vpm_fd_jacobians(fake, C.byref(p), C.byref(good()), C.byref(V.FdOut(fake, None, None)),
+                              None) == V.EINVAL

@@ -70,3 +70,12 @@ def test_emulated_replanning_cycle_matches_oracle(emu_lib):
         for key in ("g_proj", "jmin", "u_new", "x_new"):
             assert c[key] <= 1e-10, (cyc, key, row)
         assert c["gain"] <= 1e-7, (cyc, row)
+
+
+def test_emulated_fd_jacobians_match_oracle(emu_lib):
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), "fd"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-3000:]
+    row = [json.loads(x) for x in r.stdout.splitlines() if x.startswith("{")][0]
+    assert row["x_nom"] <= 1e-13 and row["A"] <= 1e-10 and row["B"] <= 1e-10, row
+    assert row["gain"] <= 1e-7, row
