@@ -474,8 +474,10 @@ __device__ __forceinline__ void solve_section(
     const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
     const R xed = xd + l * thr * st + le * (thr + u) * stp;
     const R zed = zd - l * thr * ct - le * (thr + u) * ctp;
-    const R alpha = th + ph - atan2(zed, xed);
-    const R fe = R(0.5 * a.rho * a.s_elev) * (xed * xed + zed * zed) * R(2) * sin(alpha);
+    // f_e = rho S_e V^2 sin(alpha), alpha = th + ph - atan2(zed, xed):
+    // V^2 sin(alpha) = V (sin(th + ph) xed - cos(th + ph) zed), no atan2/sin
+    const R vel_e = sqrt(xed * xed + zed * zed);
+    const R fe = R(a.rho * a.s_elev) * vel_e * (stp * xed - ctp * zed);
     const R fex = -fe * stp, fez = fe * ctp;
     const R fx = R(fwx) + fex, fz = R(fwz) + fez;
     const R ax_ = fx * R(a.inv_mass);
@@ -571,6 +573,30 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
   const int nw = nthr >> 6, ns = a.nb + 2;
   const int r = m & 63, tail = r < 32 ? r : 0;
   const int n_groups = (m >> 6) + (r >= 32 ? 1 : 0);
+  // fewer groups than waves and no tail (small wakes, latency-bound): each
+  // group's sources are split over nw / n_groups waves, partial sums added
+  // in FP64 in part order by the group's first wave
+  const int parts = tail == 0 && n_groups > 0 && n_groups < nw ? nw / n_groups : 1;
+  if (parts > 1) {
+    const int gi = wave / parts, part = wave % parts, t = gi * 64 + lane;
+    R ex = R(0), ez = R(0);
+    if (gi < n_groups && t < m) {
+      const auto s = src[head + t];
+      pass_b_sum(a, sh, s.x, s.z, rc4, (ns * part) / parts, (ns * (part + 1)) / parts, ex, ez);
+    }
+    scratch[wave * 64 + lane] = make_double2(double(ex), double(ez));
+    __syncthreads();
+    if (gi < n_groups && part == 0 && t < m) {
+      double sx = 0.0, sz = 0.0;
+      for (int q = 0; q < parts; ++q) {
+        const double2 d = scratch[(wave + q) * 64 + lane];
+        sx += d.x;
+        sz += d.y;
+      }
+      pass_b_finish(a, src, vel, k, last, head, t, sx, sz, one_decay);
+    }
+    return;
+  }
   for (int gi = wave; gi < n_groups; gi += nw) {
     const int t = gi * 64 + lane;
     if (t < m) {
@@ -1034,11 +1060,20 @@ int inverse_entries(const vpm_params *p) {
   return s * s + (p->gate ? s_te * s_te : 0);
 }
 
+// The per-wave partial sums of pass A (64 T Vec2 per wave), which pass B
+// reuses as FP64 scratch (64 double2 per wave): the larger of the two.
+template <typename R>
+size_t red_bytes(int nw, int tmax) {
+  const size_t pass_a = (size_t)nw * 64 * tmax * sizeof(Vec2<R>);
+  const size_t pass_b = (size_t)nw * 64 * sizeof(double2);
+  return pass_a > pass_b ? pass_a : pass_b;
+}
+
 // n_inv: doubles of the staged inverse(s)
 template <typename R>
 size_t lds_fixed_bytes(int nb, int n_inv, int nw, int tmax) {
   return (size_t)n_inv * sizeof(double) + (size_t)(2 * nb + 3) * sizeof(double2) +
-         (size_t)nw * 64 * tmax * sizeof(Vec2<R>) + 32 + sizeof(Shared<R>);
+         red_bytes<R>(nw, tmax) + 32 + sizeof(Shared<R>);
 }
 template <typename R> constexpr size_t lds_per_vortex() {
   return sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>);
@@ -1054,7 +1089,7 @@ int lds_layout(int cap, int nb, int nw, int tmax, KArgs &a) {
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = static_cast<int>(off);
-  off += (size_t)nw * 64 * tmax * sizeof(Vec2<R>);
+  off += red_bytes<R>(nw, tmax);
   a.off_vel = static_cast<int>(off);
   off += (size_t)cap * sizeof(Vec2<R>);
   return static_cast<int>(off);

@@ -16,7 +16,7 @@ os.environ.setdefault("EMU_N_CU", "4")
 from paper_2509_16079_amd import vpm as V  # noqa: E402
 from paper_2509_16079_amd import workloads as W  # noqa: E402
 from tests.parity import (gate_margin, gated_at_median, rel_l2, run_oracle,  # noqa: E402
-                          wake_segments, with_params)
+                          vel_segment, wake_segments, with_params)
 
 V.LIB_PATH = os.path.join(HERE, "_build", "libvpm_emu.so")
 
@@ -51,11 +51,18 @@ def cases():
         "gated": lambda: gated_at_median(W.realtime(K=4, H=8)),
         # closed loop under feedback gains (the policy inside the rollout)
         "feedback": lambda: W.realtime(K=3, H=6),
+        # one-target-per-thread shape with 138 pass-B vortices: two full
+        # groups and a tail of 10 on the third wave, whose FP64 scratch must
+        # not reach past the pass-A partial sums into the velocities
+        "tail_t1": lambda: W.workload_from_state(
+            "tail_t1", W.make_params(16), W.random_field(np.random.default_rng(9), 136), K=2, H=1,
+            eps=W.f32(np.full((2, 1), 0.05))),
     }
 
 
 TUNINGS = {"large_tuned": [(V.CLASS_SMALL, 1, 256), (V.CLASS_LARGE, 4, 128),
-                           (V.CLASS_STREAM, 2, 256)]}
+                           (V.CLASS_STREAM, 2, 256)],
+           "tail_t1": [(V.CLASS_SMALL, 1, 64)]}
 
 
 def policy_case(ctx, name):
@@ -158,14 +165,15 @@ def main(names):
             rng = np.random.default_rng(0)
             fb = dict(fb_gain=rng.normal(scale=0.5, size=(wl.H, 7)),
                       fb_xref=np.repeat(wl.g0[:1], wl.H, axis=0))
-        o = run_oracle(wl, traj=True, final_wake=True, gamma_s=True, gb_final=True, **fb)
+        o = run_oracle(wl, traj=True, final_wake=True, gamma_s=True, gb_final=True,
+                       vel_last=True, **fb)
         for prec in (V.FP32C, V.FP64):
             db = V.DeviceBatch(wl, device="cpu")
             if fb:
                 import torch
                 db.set_feedback(torch.tensor(fb["fb_gain"]), torch.tensor(fb["fb_xref"]))
             out = V.DeviceOutputs(db, device="cpu", traj=True, final_wake=True, gamma_s=True,
-                                  gb_final=True)
+                                  gb_final=True, vel_last=True)
             ctx.rollout(wl.params, db, out, prec, stream=_Stream())
             g = out.to_numpy()
             wake = max((rel_l2(a, b) for k in range(wl.K)
@@ -176,6 +184,8 @@ def main(names):
                 "gamma_s": rel_l2(g["gamma_s"], o["gamma_s"]),
                 "g_final": rel_l2(g["g_final"], o["g_final"]),
                 "gb_final": rel_l2(g["gb_final"], o["gb_final"]),
+                "vel_last": max((rel_l2(vel_segment(g, k), vel_segment(o, k))
+                                 for k in range(wl.K)), default=0.0),
                 "wake": wake,
                 "n_final_equal": bool(np.array_equal(g["n_final"], o["n_final"])),
                 "gate_margin": gate_margin(wl, o["traj"]) if wl.params.get("gate") else None,

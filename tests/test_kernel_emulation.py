@@ -27,7 +27,7 @@ def emu_lib():
 
 
 @pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large", "large_tuned",
-                                  "shed_te", "shed_none", "gated", "feedback"])
+                                  "shed_te", "shed_none", "gated", "feedback", "tail_t1"])
 def test_emulated_kernels_match_oracle(emu_lib, case):
     try:
         r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), case],
@@ -43,7 +43,7 @@ def test_emulated_kernels_match_oracle(emu_lib, case):
         assert row["n_final_equal"], row
         if row["gate_margin"] is not None:  # the decisions are robust to rounding
             assert row["gate_margin"] > 1e-5, row
-        for key in ("traj", "gamma_s", "g_final", "gb_final"):
+        for key in ("traj", "gamma_s", "g_final", "gb_final", "vel_last"):
             assert row[key] <= tol, (key, row)
         assert row["wake"] <= 10 * tol, row
 
