@@ -60,6 +60,7 @@ template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
 struct KArgs {
   int K, H, nb, S, n_wake_max, max_wake0, n_pairs, cap, n_fields;
   int mode, gate, n_inv;  // shedding mode, separation gate, inverse entries staged
+  int split_b;            // pass B may split a group's sources over idle waves
   double alpha_crit;
   double dt, chord, shed_frac, r_core, decay, rho, span, grav, mass, inertia;
   double inv_dt, inv_lb, inv_mass, inv_inertia;  // host reciprocals
@@ -573,10 +574,12 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
   const int nw = nthr >> 6, ns = a.nb + 2;
   const int r = m & 63, tail = r < 32 ? r : 0;
   const int n_groups = (m >> 6) + (r >= 32 ? 1 : 0);
-  // fewer groups than waves and no tail (small wakes, latency-bound): each
-  // group's sources are split over nw / n_groups waves, partial sums added
-  // in FP64 in part order by the group's first wave
-  const int parts = tail == 0 && n_groups > 0 && n_groups < nw ? nw / n_groups : 1;
+  // fewer groups than waves and no tail, in a launch of at most one rollout
+  // per CU (latency-bound: the idle waves are not covered by other
+  // workgroups): each group's sources are split over nw / n_groups waves,
+  // partial sums added in FP64 in part order by the group's first wave
+  const int parts =
+      a.split_b && tail == 0 && n_groups > 0 && n_groups < nw ? nw / n_groups : 1;
   if (parts > 1) {
     const int gi = wave / parts, part = wave % parts, t = gi * 64 + lane;
     R ex = R(0), ez = R(0);
@@ -1388,6 +1391,7 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.mode = p->shed_mode;
   a.gate = p->gate;
   a.alpha_crit = p->alpha_crit;
+  a.split_b = in->K <= ctx->n_cu;
   a.n_inv = inverse_entries(p);
   a.n_wake_max = p->n_wake_max;
   a.max_wake0 = in->max_wake0;
