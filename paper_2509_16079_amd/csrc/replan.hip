@@ -50,7 +50,7 @@ __global__ void init_kernel(int64_t *proj_field_off, int64_t *proj_off, int32_t 
 __global__ void batch_inputs_kernel(const double *g_proj, const double *gb_proj,
                                     const int32_t *n_proj, const double *x_eps,
                                     const double *du, const int32_t *pairs, int n_pairs,
-                                    int K, int H, int nb, double *g0, double *gb0,
+                                    int H, int nb, double *g0, double *gb0,
                                     double *u_eps, int32_t *pairs_out, int64_t *field_off,
                                     int32_t *field_of) {
   const int i = blockIdx.x;  // rollout of the batch
@@ -66,7 +66,6 @@ __global__ void batch_inputs_kernel(const double *g_proj, const double *gb_proj,
       u_eps[(size_t)i * H + n] = du && i > 0 ? du[(size_t)(i - 1) * H + n] : 0.0;
   if (t < 2 * n_pairs) pairs_out[(size_t)i * 2 * n_pairs + t] = pairs[t];
   if (t == 0) field_of[i] = 0;
-  (void)K;
 }
 
 // Bump allocator over the context's cycle workspace (256-byte aligned).
@@ -235,7 +234,7 @@ int run_replan(vpm_ctx *ctx, const vpm_params *p, const vpm_replan_in *in, vpm_r
   hipLaunchKernelGGL(shift_kernel, dim3((H + kFill - 1) / kFill), dim3(kFill), 0, stream,
                      in->u_plan, H, P, L.u_mean[0]);
   hipLaunchKernelGGL(batch_inputs_kernel, dim3(K), dim3(64), 0, stream, g_start, gb_start,
-                     L.proj_n, nullptr, nullptr, in->pairs, in->n_pairs, K, H, nb, L.g0, L.gb0,
+                     L.proj_n, nullptr, nullptr, in->pairs, in->n_pairs, H, nb, L.g0, L.gb0,
                      nullptr, L.pairs, L.field_off, L.field_of);
   VPM_HIP_TRY(hipGetLastError());
   int cur = 0;
@@ -274,7 +273,7 @@ int run_replan(vpm_ctx *ctx, const vpm_params *p, const vpm_replan_in *in, vpm_r
 
   // 3. nominal + perturbed rollouts under the new mean, then the policy
   hipLaunchKernelGGL(batch_inputs_kernel, dim3(Kb), dim3(64), 0, stream, g_start, gb_start,
-                     L.proj_n, in->x_eps, in->du, in->pairs, in->n_pairs, Kb, H, nb, L.g0, L.gb0,
+                     L.proj_n, in->x_eps, in->du, in->pairs, in->n_pairs, H, nb, L.g0, L.gb0,
                      L.u_eps_p, L.pairs, L.field_off, L.field_of);
   VPM_HIP_TRY(hipGetLastError());
   {
