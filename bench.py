@@ -30,6 +30,12 @@ Workloads (``--workload``):
                       around the nominal of one replanning cycle; reports
                       each policy's region of attraction (5 cm final
                       position error) and the time of the whole pipeline
+  nmpc                the nonlinear MPC closed in simulation: a truth model
+                      flies the 77-step manoeuvre under the policy in force
+                      while the planner replans every 10 steps (horizon
+                      shrinking to the end), with the disturbance pair
+                      absent, known to the planner or unknown to it, and
+                      the open-loop plan for comparison
   replan              one replanning cycle of the nonlinear MPC (Sec. IV-C)
                       at the paper's controller size: projection by 10 steps
                       under the policy in force, 3 MPPI iterations of 256
@@ -64,7 +70,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["realtime", "plain", "uneven", "stress", "policy",
-                                           "replan", "table1", "icsweep"],
+                                           "replan", "table1", "icsweep", "nmpc"],
                     default="realtime")
     ap.add_argument("--precision", choices=["fp32c", "fp64"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -665,6 +671,64 @@ def icsweep_main(args):
     print(json.dumps(line), flush=True)
 
 
+def nmpc_main(args):
+    import torch
+
+    from paper_2509_16079_amd import nmpc as N
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    prec_name = args.precision or "fp32c"
+    prec = V.FP32C if prec_name == "fp32c" else V.FP64
+    c = W.replan_case()
+    ctx = V.Context(0)
+    tuning = apply_tuning(ctx, args.tuning)
+    N.simulate(ctx, c, "compensated", prec)          # warm-up (inverses, workspaces)
+    res, lat = {}, []
+    t0 = time.perf_counter()
+    for sc in N.SCENARIOS:
+        r = N.simulate(ctx, c, sc, prec)
+        err, cost = N.final_error(c, r["traj"])
+        res[sc] = {"final_pos_err_m": err, "final_cost": cost,
+                   "replan_ms": [round(float(x), 3) for x in r["replan_ms"]]}
+        lat.extend(r["replan_ms"])
+    wall = 1e3 * (time.perf_counter() - t0)
+    ol = N.open_loop(ctx, c, prec)
+    err, cost = N.final_error(c, ol["traj"])
+    res["open_loop_with_disturbance"] = {"final_pos_err_m": err, "final_cost": cost}
+    torch.cuda.synchronize()
+    line = {
+        "metric": "closed-loop NMPC in simulation: final perch error per scenario and "
+                  "replanning latency",
+        "value": float(np.percentile(lat, 50)), "unit": "ms (replanning cycle, p50)",
+        "n_gpus": 1, "steps": len(lat), "warmup": 1, "ms_per_step": float(np.mean(lat)),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == V.FP32C else "f64", "data": "synthetic",
+        "config": {"workload": "nmpc: 77-step manoeuvre at dt=10 ms, replanning every 10 "
+                               "steps (3 x 256 MPPI rollouts, 257 policy rollouts), goal x_d of "
+                               "Sec. IV-A, one disturbance pair", "precision": prec_name},
+        "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)),
+        "replan_budget_ms": 100.0,
+        "scenarios": res,
+        "simulation_wall_ms": wall,
+        "tuning": tuning,
+        "kernel_timing": "wall time of each vpm_replan call to its completion",
+    }
+    if not args.no_cpu_baseline:
+        from oracle import nmpc as ON
+        t0 = time.perf_counter()
+        o = ON.simulate(c, "compensated")
+        line["cpu_baseline"] = {"value": 1e3 * (time.perf_counter() - t0), "unit": "ms",
+                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+                                "kind": "oracle",
+                                "sample": "the compensated scenario's whole simulation (FP64)"}
+        g64 = N.simulate(ctx, c, "compensated", V.FP64)
+        line["error_vs_oracle"] = {"fp64_truth_traj_rel_l2": _rel_l2(g64["traj"], o["traj"]),
+                                   "fp64_jmin_rel_l2": _rel_l2(g64["jmin"], o["jmin"])}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -680,6 +744,8 @@ def main():
         return table1_main(args)
     if args.workload == "icsweep":
         return icsweep_main(args)
+    if args.workload == "nmpc":
+        return nmpc_main(args)
     import torch
 
     from paper_2509_16079_amd import vpm as V
