@@ -75,14 +75,15 @@ def sweep(ctx, wl, classes, reps=3, log=print):
 def class_capacities(wl):
     """cap_small / cap_large of the library's class rule for this plate, at
     the default shapes (4-wave workgroups within a quarter of the 160 KB LDS,
-    16-wave within all of it): fixed bytes per rollout plus 24 B per vortex."""
+    16-wave within all of it): fixed bytes per rollout plus 24 B per vortex
+    (the small class 40 B: it also holds the scaled pass-A copy)."""
     nb = wl.params["n_bound"]
     S = nb + 2
 
-    def cap(nw, tmax, budget):
+    def cap(nw, tmax, budget, per_vortex):
         fixed = S * S * 8 + (2 * nb + 3) * 16 + nw * 64 * tmax * 8 + 32 + 2600
-        return (budget - fixed) // 24
-    return cap(4, 4, 163840 // 4), cap(16, 2, 163840)
+        return (budget - fixed) // per_vortex
+    return cap(4, 4, 163840 // 4, 40), cap(16, 2, 163840, 24)
 
 
 def table_entry(wl_name, wl, best):

@@ -30,9 +30,12 @@
 //    targets, so each target sums its sources in strict FIFO order. It
 //    serves wakes too large for LDS (tens of thousands of vortices).
 //
-// The N^2 work is pure VALU: 8 FP32 ops + 1 v_rsq_f32 per regularised pair,
+// The N^2 work is pure VALU: per regularised pair 7 FP32 ops + 1 v_rsq_f32 on
+// sources pre-scaled by 1/Gamma (small and streamed FP32 classes), 8 + 1 on
+// unscaled sources (FP32 large class, FP64),
 // no MFMA (the sum is not a dense contraction).
 #include <cmath>
+#include <type_traits>
 
 #include "vpm_internal.h"
 #include "wave_ops.h"
@@ -53,6 +56,25 @@ struct alignas(32) Src64 {
 template <typename R> struct SrcOf;
 template <> struct SrcOf<float> { using type = Src32; };
 template <> struct SrcOf<double> { using type = Src64; };
+
+// Pass-A source of the FP32 kernels, pre-scaled by q = 1/g: with dx' = q dx
+// and dz' = q dz, (dx'^2 + dz'^2)^2 + (q rc)^4 = q^4 (r^4 + rc^4), so its
+// inverse square root times dz' is g dz / sqrt(r^4 + rc^4), the regularised
+// term, for 7 VALU operations and v_rsq_f32 instead of 8 and v_rsq_f32 (the
+// multiply by g disappears into the scaling). FP64 sources stay unscaled.
+struct alignas(16) Scl32 {
+  float px, pz, q, cs;  // q x, q z, q, (q rc)^4
+};
+template <typename R> struct PassAOf;
+template <> struct PassAOf<float> { using type = Scl32; };
+template <> struct PassAOf<double> { using type = Src64; };
+
+// Which LDS kernels keep a scaled copy of the wake (16 B more per vortex):
+// the FP32 small class. The FP32 large class reads its wake unscaled: its
+// capacity is what LDS holds, and the copy would send rollouts of 3k-5k
+// vortices to the streamed class, which runs them slower than the unscaled
+// pair costs. The streamed class scales each staged tile.
+template <typename R, int NW> constexpr bool lds_scaled() { return sizeof(R) == 4 && NW == 4; }
 
 template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
 
@@ -77,7 +99,7 @@ struct KArgs {
   int32_t *status, *n_final, *n_vel_last;
   int64_t *pair_count;
   const int64_t *wake_off;
-  int off_vsurf, off_red, off_vel, off_kinv;  // byte offsets into dynamic LDS
+  int off_vsurf, off_red, off_vel, off_kinv, off_scl;  // byte offsets into dynamic LDS
   void *ws_src, *ws_vel;  // streaming workspace: one slot of `cap` per block
 };
 
@@ -129,6 +151,94 @@ __device__ inline void sing_term(R dx, R dz, R g, R &vx, R &vz) {
   vz += dx * k;
 }
 
+// Scaled form of a source at (x, z) with strength g = Gamma/(2 pi). A source
+// with |g| < 1e-30 gets q = 0 and cs = +inf and adds exactly 0 (an exactly
+// zero strength, e.g. a terminated disturbance pair, is the case that
+// matters; with r_core >= 1e-6 m such a source moves a target by less than
+// 1e-24 m/s). Where q^4 (r^4 + rc^4) exceeds the FP32 range the rsq of +inf
+// is 0: the term g r / sqrt(r^4 + rc^4) is then below M^(-1/4) = 2.3e-10 m/s
+// (M the largest float), since sqrt(r^4 + rc^4) > sqrt(M) g^2 and r^2 is at
+// most that root. The floor at the smallest normal number keeps the inverse
+// square root finite for coincident points when (q rc)^4 underflows. q = 1/g
+// to 1 ulp (v_rcp_f32): the term's strength is 1/q, within 1.2e-7 of g, as
+// close as storing g in binary32.
+__device__ inline Scl32 scale_source(float x, float z, float g, float rc) {
+  if (fabsf(g) < 1e-30f) return Scl32{0.0f, 0.0f, 0.0f, INFINITY};
+  const float q = fabsf(g) <= 3.40282347e38f ? __builtin_amdgcn_rcpf(g) : __builtin_nanf("");
+  const float rq = rc * q, rq2 = rq * rq;
+  return Scl32{x * q, z * q, q, fmaxf(rq2 * rq2, 1.17549435e-38f)};
+}
+
+// Regularised term of a scaled source at target (tx, tz): 2 FMA for dx', dz',
+// mul + FMA for r'^2, FMA for r'^4 + cs, v_rsq_f32, 2 FMA.
+__device__ inline void reg_term_scaled(float tx, float tz, const Scl32 &v, float &vx,
+                                       float &vz) {
+  const float dx = fmaf(tx, v.q, -v.px), dz = fmaf(tz, v.q, -v.pz);
+  const float r2 = fmaf(dz, dz, dx * dx);
+  const float k = rsq(fmaf(r2, r2, v.cs));
+  vx = fmaf(-dz, k, vx);
+  vz = fmaf(dx, k, vz);
+}
+
+__device__ inline void pair_term(float tx, float tz, const Scl32 &v, float, float &vx,
+                                 float &vz) {
+  reg_term_scaled(tx, tz, v, vx, vz);
+}
+__device__ inline void pair_term(float tx, float tz, const Src32 &v, float rc4, float &vx,
+                                 float &vz) {
+  reg_term(tx - v.x, tz - v.z, v.g, rc4, vx, vz);
+}
+__device__ inline void pair_term(double tx, double tz, const Src64 &v, double rc4, double &vx,
+                                 double &vz) {
+  reg_term(tx - v.x, tz - v.z, v.g, rc4, vx, vz);
+}
+
+// A wake vortex is a pass-A target and a source. K'(0) = 0 makes its term on
+// itself vanish, but in scaled form dx' = fma(x, q, -RN(q x)) is the rounding
+// error of q x, not 0: the self term is of order g |x| 2^-24 / rc^2. It is
+// recomputed with the same operations and taken out of the vortex's velocity
+// (the streamed class at the end of pass A, the LDS small class in pass B).
+__device__ inline void remove_self(float x, float z, const Scl32 &v, double &vx, double &vz) {
+  float ax = 0.0f, az = 0.0f;
+  reg_term_scaled(x, z, v, ax, az);
+  vx -= double(ax);
+  vz -= double(az);
+}
+
+// Pass-B upkeep of the scaled copy for wake entry p (LDS small class; a
+// no-op without a copy), prepared before the pass-B sum so that its loads
+// and v_rcp_f32 overlap it: the entry's pass-A self term, when it was a
+// pass-A source this step (vortices shed this step were not), and q and cs
+// of its decayed strength g_new for the rewritten entry.
+struct Upkeep {
+  double sx, sz;  // self term to take out of the velocity
+  float q, cs;
+};
+template <typename S>
+__device__ inline Upkeep upkeep(const Scl32 *scl, int p, const S &s, bool was_source,
+                                float g_new, float rc) {
+  Upkeep u{0.0, 0.0, 0.0f, 0.0f};
+  if (!scl) return u;
+  if (was_source) remove_self(float(s.x), float(s.z), scl[p], u.sx, u.sz);
+  const Scl32 n = scale_source(0.0f, 0.0f, g_new, rc);
+  u.q = n.q;
+  u.cs = n.cs;
+  return u;
+}
+
+// Pass-A source entry of an FP32 or FP64 wake entry.
+__device__ inline Scl32 pass_a_source(const Src32 &s, float rc) {
+  return scale_source(s.x, s.z, s.g, rc);
+}
+__device__ inline Src64 pass_a_source(const Src64 &s, double) { return s; }
+
+// Keep entry p of the scaled copy (FP32 LDS kernels; null otherwise) in step
+// with the wake entry s just written.
+template <typename S>
+__device__ inline void rescale(Scl32 *scl, int p, const S &s, float rc) {
+  if (scl) scl[p] = scale_source(float(s.x), float(s.z), float(s.g), rc);
+}
+
 // Knuth's TwoSum: s + c absorbs t with the rounding error of s + t kept in c.
 __device__ inline void two_sum(float &s, float &c, float t) {
   float u = s + t;
@@ -158,8 +268,8 @@ __device__ inline void fold_tile(R (&sx)[T], R (&sz)[T], R (&cx)[T], R (&cz)[T],
 
 // Sources [s_lo, s_hi) of `src` onto the T targets of this lane, folded
 // every TILE sources.
-template <typename R, int T, int TILE>
-__device__ inline void accumulate(const typename SrcOf<R>::type *__restrict__ src,
+template <typename R, int T, int TILE, typename S>
+__device__ inline void accumulate(const S *__restrict__ src,
                                   int s_lo, int s_hi, const R (&tx)[T],
                                   const R (&tz)[T], R rc4, R (&sx)[T], R (&sz)[T],
                                   R (&cx)[T], R (&cz)[T]) {
@@ -170,9 +280,9 @@ __device__ inline void accumulate(const typename SrcOf<R>::type *__restrict__ sr
     for (int j = 0; j < T; ++j) ax[j] = az[j] = R(0);
 #pragma unroll 4
     for (int q = s0; q < s1; ++q) {
-      const typename SrcOf<R>::type v = src[q];
+      const S v = src[q];
 #pragma unroll
-      for (int j = 0; j < T; ++j) reg_term(tx[j] - v.x, tz[j] - v.z, v.g, rc4, ax[j], az[j]);
+      for (int j = 0; j < T; ++j) pair_term(tx[j], tz[j], v, rc4, ax[j], az[j]);
     }
     fold_tile<R, T>(sx, sz, cx, cz, ax, az);
   }
@@ -282,7 +392,7 @@ __device__ __noinline__ double wing_aoa(double th, double xd, double zd, double 
 // plain open-loop instances a few per cent.
 template <typename R, bool EXT>
 __device__ void prologue(const KArgs &a, Shared<R> &sh,
-                         typename SrcOf<R>::type *src, int n) {
+                         typename SrcOf<R>::type *src, Scl32 *scl, int n) {
   geometry(a, sh);
   int mode = a.mode;
   if constexpr (EXT) {
@@ -310,6 +420,8 @@ __device__ void prologue(const KArgs &a, Shared<R> &sh,
     if (hits_plate(sh, a.chord, src[pa].x, src[pa].z, src[pb].x, src[pb].z)) {
       src[pa].g = R(0);
       src[pb].g = R(0);
+      rescale(scl, pa, src[pa], float(a.r_core));
+      rescale(scl, pb, src[pb], float(a.r_core));
       sh.pa[q] = sh.pb[q] = -1;
     }
   }
@@ -320,7 +432,7 @@ __device__ void prologue(const KArgs &a, Shared<R> &sh,
 // the workgroup.
 template <typename R>
 __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *src,
-                      int k, int tid, int nthr) {
+                      Scl32 *scl, int k, int tid, int nthr) {
   using Src = typename SrcOf<R>::type;
   const int nb = a.nb;
   const int fo = a.field_of ? a.field_of[k] : k;
@@ -340,8 +452,10 @@ __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *sr
     }
     return false;
   }
-  for (int q = tid; q < n0; q += nthr)
+  for (int q = tid; q < n0; q += nthr) {
     src[q] = Src{R(a.wx[f0 + q]), R(a.wz[f0 + q]), R(a.wg[f0 + q] * kInv2Pi), R(0)};
+    rescale(scl, q, src[q], float(a.r_core));
+  }
   if (tid < 7) {
     sh.g[tid] = R(a.g0[7 * k + tid]);
     if (a.traj) a.traj[(size_t)k * (a.H + 1) * 7 + tid] = a.g0[7 * k + tid];
@@ -538,14 +652,21 @@ __device__ inline void pass_b_sum(const KArgs &a, const Shared<R> &sh, R x, R z,
 
 // Wake vortex t of the step: total velocity (pass A + edge and bound terms),
 // optional output, Euler advection and decay.
+// With a scaled copy, `up` (from upkeep) removes the pass-A self term (sx, sz
+// hold its negation) and rewrites the copy's entry as scale_source would.
 template <typename R>
 __device__ inline void pass_b_finish(const KArgs &a, typename SrcOf<R>::type *src,
-                                     const Vec2<R> *vel, int k, bool last, int head, int t,
-                                     double ex, double ez, R one_decay) {
+                                     Scl32 *scl, const Vec2<R> *vel, int k, bool last,
+                                     int head, int t, double ex, double ez, R one_decay,
+                                     const Upkeep &up) {
   const int p = head + t;
   auto s = src[p];
   const Vec2<R> v0 = vel[p];
-  const double vx = double(v0.x) + ex, vz = double(v0.z) + ez;
+  double vx = double(v0.x) + ex, vz = double(v0.z) + ez;
+  if constexpr (sizeof(R) == 4) {
+    vx += up.sx;
+    vz += up.sz;
+  }
   if (last && a.vel_last) {
     double *o = a.vel_last + 2 * (a.wake_off[k] + t);
     o[0] = vx;
@@ -556,6 +677,8 @@ __device__ inline void pass_b_finish(const KArgs &a, typename SrcOf<R>::type *sr
   s.z = s.z + dtr * R(vz);
   s.g = s.g * one_decay;
   src[p] = s;
+  if constexpr (sizeof(R) == 4)
+    if (scl) scl[p] = Scl32{s.x * up.q, s.z * up.q, up.q, up.cs};
 }
 
 // All waves: the m wake vortices in groups of 64 (group i to wave i mod NW),
@@ -564,11 +687,12 @@ __device__ inline void pass_b_finish(const KArgs &a, typename SrcOf<R>::type *sr
 // added in FP64 in part order through `scratch` (64 double2 per wave).
 template <typename R>
 __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
-                                       typename SrcOf<R>::type *src,
+                                       typename SrcOf<R>::type *src, Scl32 *scl,
                                        const Vec2<R> *vel, int k, bool last,
-                                       int head, int m, int tid, int nthr,
+                                       int head, int m, int n_src, int tid, int nthr,
                                        double2 *scratch) {
   const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  const float rcf = float(a.r_core);
   const R one_decay = R(1.0 - a.decay * a.dt);
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nw = nthr >> 6, ns = a.nb + 2;
@@ -583,8 +707,10 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
   if (parts > 1) {
     const int gi = wave / parts, part = wave % parts, t = gi * 64 + lane;
     R ex = R(0), ez = R(0);
+    Upkeep up{};
     if (gi < n_groups && t < m) {
       const auto s = src[head + t];
+      if (part == 0) up = upkeep(scl, head + t, s, t < n_src, s.g * one_decay, rcf);
       pass_b_sum(a, sh, s.x, s.z, rc4, (ns * part) / parts, (ns * (part + 1)) / parts, ex, ez);
     }
     scratch[wave * 64 + lane] = make_double2(double(ex), double(ez));
@@ -596,7 +722,7 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
         sx += d.x;
         sz += d.y;
       }
-      pass_b_finish(a, src, vel, k, last, head, t, sx, sz, one_decay);
+      pass_b_finish(a, src, scl, vel, k, last, head, t, sx, sz, one_decay, up);
     }
     return;
   }
@@ -604,16 +730,19 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
     const int t = gi * 64 + lane;
     if (t < m) {
       const auto s = src[head + t];
+      const Upkeep up = upkeep(scl, head + t, s, t < n_src, s.g * one_decay, rcf);
       R ex = R(0), ez = R(0);
       pass_b_sum(a, sh, s.x, s.z, rc4, 0, ns, ex, ez);
-      pass_b_finish(a, src, vel, k, last, head, t, double(ex), double(ez), one_decay);
+      pass_b_finish(a, src, scl, vel, k, last, head, t, double(ex), double(ez), one_decay, up);
     }
   }
   if (tail > 0 && wave == n_groups % nw) {
     const int t0 = n_groups * 64, g = 64 / tail, tt = lane % tail, part = lane / tail;
     R ex = R(0), ez = R(0);
+    Upkeep up{};
     if (part < g) {
       const auto s = src[head + t0 + tt];
+      if (part == 0) up = upkeep(scl, head + t0 + tt, s, t0 + tt < n_src, s.g * one_decay, rcf);
       pass_b_sum(a, sh, s.x, s.z, rc4, (ns * part) / g, (ns * (part + 1)) / g, ex, ez);
     }
     double2 *sc = scratch + wave * 64;
@@ -628,7 +757,7 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
         sx += d.x;
         sz += d.y;
       }
-      pass_b_finish(a, src, vel, k, last, head, t0 + lane, sx, sz, one_decay);
+      pass_b_finish(a, src, scl, vel, k, last, head, t0 + lane, sx, sz, one_decay, up);
     }
   }
 }
@@ -637,7 +766,7 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
 // it is the last step, the next step's prologue.
 template <typename R, bool EXT>
 __device__ void epilogue(const KArgs &a, Shared<R> &sh,
-                         typename SrcOf<R>::type *src, int k, int n, int n_w) {
+                         typename SrcOf<R>::type *src, Scl32 *scl, int k, int n, int n_w) {
   using Src = typename SrcOf<R>::type;
   const int nb = a.nb, m = n_w + sh.n_shed;
   const bool last = (n == a.H - 1);
@@ -646,6 +775,7 @@ __device__ void epilogue(const KArgs &a, Shared<R> &sh,
   while (a.n_wake_max > 0 && cnt > a.n_wake_max && cnt >= 2) {
     const Src s0 = src[h], s1 = src[h + 1];
     src[h + 1] = Src{R(0.5) * (s0.x + s1.x), R(0.5) * (s0.z + s1.z), s0.g + s1.g, R(0)};
+    rescale(scl, h + 1, src[h + 1], float(a.r_core));
     for (int q = 0; q < kMaxPairs; ++q)
       if (sh.pa[q] == h || sh.pa[q] == h + 1 || sh.pb[q] == h || sh.pb[q] == h + 1)
         sh.pa[q] = sh.pb[q] = -1;
@@ -659,7 +789,7 @@ __device__ void epilogue(const KArgs &a, Shared<R> &sh,
     for (int i = 0; i < 7; ++i)
       a.traj[((size_t)k * (a.H + 1) + n + 1) * 7 + i] = double(sh.gn[i]);
   if (last && a.n_vel_last) a.n_vel_last[k] = m;
-  if (!last) prologue<R, EXT>(a, sh, src, n + 1);
+  if (!last) prologue<R, EXT>(a, sh, src, scl, n + 1);
 }
 
 // Final outputs of rollout k.
@@ -727,9 +857,9 @@ __device__ inline int claim(const Queue &q, Shared<R> &sh, int tid,
 
 // ---------------------------------------------------------------- LDS path
 
-template <typename R, int T, int NW, int TILE>
+template <typename R, int T, int NW, int TILE, typename S>
 __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
-                                 const typename SrcOf<R>::type *src, Vec2<R> *red,
+                                 const typename SrcOf<R>::type *src, const S *pa, Vec2<R> *red,
                                  int c0, int NT, int head, int s_lo, int s_hi,
                                  int lane, int wave) {
   const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
@@ -739,7 +869,7 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
     target_pos(a, sh, src, c0 + lane + 64 * j, NT, head, tx[j], tz[j]);
     sx[j] = sz[j] = cx[j] = cz[j] = R(0);
   }
-  accumulate<R, T, TILE>(src, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
+  accumulate<R, T, TILE>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
   Vec2<R> *out = red + wave * 64 * T;
 #pragma unroll
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
@@ -749,9 +879,9 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
 // l / r of g = 64 / r equal parts of this wave's sources, so g r lanes work
 // instead of r. The partials land where a T = 1 chunk puts them, lane l at
 // red[wave 64 + l], and are added per target over waves, then parts.
-template <typename R, int NW, int TILE>
+template <typename R, int NW, int TILE, typename S>
 __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
-                                const typename SrcOf<R>::type *src, Vec2<R> *red,
+                                const typename SrcOf<R>::type *src, const S *pa, Vec2<R> *red,
                                 int c0, int NT, int head, int s_lo, int s_hi,
                                 int r, int lane, int wave) {
   const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
@@ -760,7 +890,7 @@ __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
   target_pos(a, sh, src, c0 + t, NT, head, tx[0], tz[0]);
   if (q < g) {
     const int len = s_hi - s_lo;
-    accumulate<R, 1, TILE>(src, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
+    accumulate<R, 1, TILE>(pa, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
                      sx, sz, cx, cz);
   }
   red[wave * 64 + lane] = Vec2<R>{sx[0] + cx[0], sz[0] + cz[0]};
@@ -809,6 +939,11 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
   Vec2<R> *red = reinterpret_cast<Vec2<R> *>(lds + a.off_red);
   Vec2<R> *vel = reinterpret_cast<Vec2<R> *>(lds + a.off_vel);
   double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
+  // the scaled copy of the wake that pass A reads, or the wake itself
+  constexpr bool SCL = lds_scaled<R, NW>();
+  using PA = std::conditional_t<SCL, Scl32, Src>;
+  Scl32 *scl = SCL ? reinterpret_cast<Scl32 *>(lds + a.off_scl) : nullptr;
+  const PA *pa = reinterpret_cast<const PA *>(SCL ? lds + a.off_scl : lds);
 
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index as a scalar (every lane is active here), so loops bounded by
@@ -822,12 +957,12 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
     const int k = claim(qu, sh, tid, fallback);
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, k, tid, kThr)) continue;
+    if (!setup(a, sh, src, scl, k, tid, kThr)) continue;
     __syncthreads();
 
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, EXT>(a, sh, src, 0);
+        if (tid == 0) prologue<R, EXT>(a, sh, src, scl, 0);
         __syncthreads();
       }
       rotate_priority(sh.slot, n);
@@ -848,12 +983,12 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         while (T > 1 && 64 * T > rem) T >>= 1;
         const int tail = rem < 32 ? rem : 0;  // tails of 32..63 keep a lane each
         if (tail) {
-          lds_pass_a_tail<R, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
+          lds_pass_a_tail<R, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
         } else {
           switch (T) {
-            case 1: lds_pass_a_chunk<R, 1, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW, TILE>(a, sh, src, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 1: lds_pass_a_chunk<R, 1, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
           }
         }
         __syncthreads();
@@ -870,10 +1005,11 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
             }
           }
           const int tt = c0 + t;
-          if (tt < n_surf)
+          if (tt < n_surf) {
             vsurf[tt] = make_double2(vx, vz);
-          else
-            vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};
+          } else {
+            vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};  // self term: pass B
+          }
         }
         __syncthreads();
         c0 += span;
@@ -883,10 +1019,10 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
                       EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
-      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
+      pass_b(a, sh, src, scl, vel, k, n == a.H - 1, head, n_w + n_shed, n_w, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, EXT>(a, sh, src, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
       __syncthreads();
     }
     finish(a, sh, src, k, tid, kThr);
@@ -898,7 +1034,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 template <typename R, int T, int NW, int TILE>
 __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
                                     const typename SrcOf<R>::type *src,
-                                    typename SrcOf<R>::type *tile, Vec2<R> *vel,
+                                    typename PassAOf<R>::type *tile, Vec2<R> *vel,
                                     double2 *vsurf, int c0, int NT, int head,
                                     int n_w, int tid, int lane, int wave) {
   const int n_surf = 2 * a.nb + 3;
@@ -912,7 +1048,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
   }
   for (int s0 = 0; s0 < n_w; s0 += kStreamTile) {
     const int cnt = min(kStreamTile, n_w - s0);
-    for (int q = tid; q < cnt; q += 64 * NW) tile[q] = src[head + s0 + q];
+    for (int q = tid; q < cnt; q += 64 * NW) tile[q] = pass_a_source(src[head + s0 + q], rc);
     __syncthreads();
     accumulate<R, T, TILE>(tile, 0, cnt, tx, tz, rc4, sx, sz, cx, cz);
     __syncthreads();
@@ -921,11 +1057,14 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
   for (int j = 0; j < T; ++j) {
     const int t = t0 + j * 64 * NW;
     if (t >= NT) continue;
-    const double vx = double(sx[j]) + double(cx[j]), vz = double(sz[j]) + double(cz[j]);
-    if (t < n_surf)
+    double vx = double(sx[j]) + double(cx[j]), vz = double(sz[j]) + double(cz[j]);
+    if (t < n_surf) {
       vsurf[t] = make_double2(vx, vz);
-    else
-      vel[head + t - n_surf] = Vec2<R>{R(vx), R(vz)};
+    } else {
+      const int i = head + t - n_surf;
+      if constexpr (sizeof(R) == 4) remove_self(tx[j], tz[j], pass_a_source(src[i], rc), vx, vz);
+      vel[i] = Vec2<R>{R(vx), R(vz)};
+    }
   }
 }
 
@@ -938,7 +1077,8 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
   constexpr int kThr = 64 * NW;
   extern __shared__ __align__(32) unsigned char lds[];
   __shared__ Shared<R> sh;
-  Src *tile = reinterpret_cast<Src *>(lds);
+  auto *tile = reinterpret_cast<typename PassAOf<R>::type *>(lds);
+  Scl32 *const scl = nullptr;  // pass A converts each staged tile
   double2 *vsurf = reinterpret_cast<double2 *>(lds + a.off_vsurf);
   double *kinv = reinterpret_cast<double *>(lds + a.off_kinv);
   Src *src = reinterpret_cast<Src *>(a.ws_src) + (size_t)blockIdx.x * a.cap;
@@ -962,11 +1102,11 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     }
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, k, tid, kThr)) continue;
+    if (!setup(a, sh, src, scl, k, tid, kThr)) continue;
     __syncthreads();
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, EXT>(a, sh, src, 0);
+        if (tid == 0) prologue<R, EXT>(a, sh, src, scl, 0);
         __syncthreads();
       }
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
@@ -993,10 +1133,10 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
         solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
                       EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
-      pass_b(a, sh, src, vel, k, n == a.H - 1, head, n_w + n_shed, tid, kThr,
+      pass_b(a, sh, src, scl, vel, k, n == a.H - 1, head, n_w + n_shed, n_w, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, EXT>(a, sh, src, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
       __syncthreads();
     }
     finish(a, sh, src, k, tid, kThr);
@@ -1078,14 +1218,21 @@ size_t lds_fixed_bytes(int nb, int n_inv, int nw, int tmax) {
   return (size_t)n_inv * sizeof(double) + (size_t)(2 * nb + 3) * sizeof(double2) +
          red_bytes<R>(nw, tmax) + 32 + sizeof(Shared<R>);
 }
-template <typename R> constexpr size_t lds_per_vortex() {
-  return sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>);
+// Per vortex: the wake entry, its pass-A velocity and (FP32) its scaled copy.
+template <typename R, int NW> constexpr size_t scaled_bytes() {
+  return lds_scaled<R, NW>() ? sizeof(Scl32) : 0;
+}
+template <typename R, int NW> constexpr size_t lds_per_vortex() {
+  return sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>) + scaled_bytes<R, NW>();
 }
 
-template <typename R>
-int lds_layout(int cap, int nb, int nw, int tmax, KArgs &a) {
+template <typename R, int NW>
+int lds_layout(int cap, int nb, int tmax, KArgs &a) {
+  constexpr int nw = NW;
   size_t off = 0;
   off += (size_t)cap * sizeof(typename SrcOf<R>::type);
+  a.off_scl = static_cast<int>(off);
+  off += (size_t)cap * scaled_bytes<R, NW>();
   off = (off + 15) & ~size_t(15);
   a.off_kinv = static_cast<int>(off);
   off += (size_t)a.n_inv * sizeof(double);
@@ -1100,7 +1247,8 @@ int lds_layout(int cap, int nb, int nw, int tmax, KArgs &a) {
 
 template <typename R>
 int stream_layout(int nb, KArgs &a) {
-  size_t off = (size_t)kStreamTile * sizeof(typename SrcOf<R>::type);
+  size_t off = (size_t)kStreamTile * sizeof(typename PassAOf<R>::type);
+  a.off_scl = 0;
   a.off_kinv = static_cast<int>(off);
   off += (size_t)a.n_inv * sizeof(double);
   a.off_vsurf = static_cast<int>(off);
@@ -1124,7 +1272,7 @@ template <typename R, int TMAX, int MINW, int NW, int TILE>
 int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
                hipStream_t stream) {
   a.cap = cap;
-  const int lds = lds_layout<R>(cap, a.nb, NW, TMAX, a);
+  const int lds = lds_layout<R, NW>(cap, a.nb, TMAX, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
                                    " does not fit the LDS-resident kernel");
@@ -1160,10 +1308,10 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
 }
 
 // Largest capacity a workgroup of the LDS kernel can hold within `bytes`.
-template <typename R>
-int lds_capacity(int nb, int n_inv, int nw, int tmax, size_t bytes) {
-  const size_t fixed = lds_fixed_bytes<R>(nb, n_inv, nw, tmax);
-  return bytes > fixed ? static_cast<int>((bytes - fixed) / lds_per_vortex<R>()) : 0;
+template <typename R, int NW>
+int lds_capacity(int nb, int n_inv, int tmax, size_t bytes) {
+  const size_t fixed = lds_fixed_bytes<R>(nb, n_inv, NW, tmax);
+  return bytes > fixed ? static_cast<int>((bytes - fixed) / lds_per_vortex<R, NW>()) : 0;
 }
 
 // Kernel instance for a class's tuning (targets per thread x compensation
@@ -1234,8 +1382,8 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
   const int cap = a.cap;  // max_wake0 + 2H
   const Tune t_s = class_tune<R>(ctx, VPM_CLASS_SMALL), t_l = class_tune<R>(ctx, VPM_CLASS_LARGE);
   const Tune t_x = class_tune<R>(ctx, VPM_CLASS_STREAM);
-  const int cap_small = lds_capacity<R>(a.nb, a.n_inv, kNwSmall, t_s.tmax, ctx->max_lds / 4);
-  const int cap_large = lds_capacity<R>(a.nb, a.n_inv, kNwLarge, t_l.tmax, ctx->max_lds);
+  const int cap_small = lds_capacity<R, kNwSmall>(a.nb, a.n_inv, t_s.tmax, ctx->max_lds / 4);
+  const int cap_large = lds_capacity<R, kNwLarge>(a.nb, a.n_inv, t_l.tmax, ctx->max_lds);
   const Queue none{nullptr, nullptr, nullptr, 0};
   const bool stream_only = path == VPM_PATH_STREAM;
   if (a.n_fields == 1 || path == VPM_PATH_LDS || stream_only) {
@@ -1349,7 +1497,7 @@ template <typename R>
 int reserve_batch(vpm_ctx *ctx, int nb, int n_inv, int K, int cap, int n_fields) {
   constexpr int kNwLarge = sizeof(R) == 4 ? 16 : 8;
   const int cap_large =
-      lds_capacity<R>(nb, n_inv, kNwLarge, class_tune<R>(ctx, VPM_CLASS_LARGE).tmax, ctx->max_lds);
+      lds_capacity<R, kNwLarge>(nb, n_inv, class_tune<R>(ctx, VPM_CLASS_LARGE).tmax, ctx->max_lds);
   const int path = ctx->path;
   std::lock_guard<std::mutex> lock(ctx->ws_mu);
   if (path == VPM_PATH_STREAM || (path == VPM_PATH_AUTO && cap > cap_large)) {
@@ -1377,7 +1525,7 @@ int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wak
 }
 
 int lds_resident_capacity(int nb) {
-  return lds_capacity<float>(nb, (nb + 2) * (nb + 2), 16, 2, 163840);
+  return lds_capacity<float, 16>(nb, (nb + 2) * (nb + 2), 2, 163840);
 }
 
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,

@@ -25,6 +25,14 @@ class _Stream:
     cuda_stream = 0
 
 
+def _scaled_edge_field():
+    x, z, g = W.random_field(np.random.default_rng(11), 60)
+    x = np.concatenate([x, [30.0, 30.0, 1.2, 1.5, 2.0, 2.4, 0.8]])
+    z = np.concatenate([z, [0.25, -0.25, 0.1, -0.2, 0.3, -0.1, 0.05]])
+    g = np.concatenate([g, [-2.0, 2.0, 0.0, 0.0, 1e-33, 1e-20, -1e-12]])
+    return W.f32(x), W.f32(z), W.f32(g)
+
+
 def cases():
     return {
         # empty initial wake over several steps, N_b = 16
@@ -51,6 +59,13 @@ def cases():
         "gated": lambda: gated_at_median(W.realtime(K=4, H=8)),
         # closed loop under feedback gains (the policy inside the rollout)
         "feedback": lambda: W.realtime(K=3, H=6),
+        # sources the FP32 kernels pre-scale by 1/Gamma at their edges: a
+        # strong pair 30 m downstream (its self terms, were they not removed,
+        # would be ~6e-3 m/s against a mutual 0.6 m/s), zero strengths, and
+        # strengths below the 1e-30 cut and in the overflow range
+        "scaled_edges": lambda: W.workload_from_state(
+            "scaled_edges", W.make_params(16), _scaled_edge_field(), K=2, H=3,
+            eps=W.f32(np.full((2, 3), 0.05))),
         # one-target-per-thread shape with 138 pass-B vortices: two full
         # groups and a tail of 10 on the third wave, whose FP64 scratch must
         # not reach past the pass-A partial sums into the velocities

@@ -27,7 +27,8 @@ def emu_lib():
 
 
 @pytest.mark.parametrize("case", ["empty", "realtime", "nb64", "uneven", "large", "large_tuned",
-                                  "shed_te", "shed_none", "gated", "feedback", "tail_t1"])
+                                  "shed_te", "shed_none", "gated", "feedback", "scaled_edges",
+                                  "tail_t1"])
 def test_emulated_kernels_match_oracle(emu_lib, case):
     try:
         r = subprocess.run([sys.executable, os.path.join(EMU, "run_cases.py"), case],
