@@ -31,8 +31,8 @@
 //    serves wakes too large for LDS (tens of thousands of vortices).
 //
 // The N^2 work is pure VALU: per regularised pair 7 FP32 ops + 1 v_rsq_f32 on
-// sources pre-scaled by 1/Gamma (small and streamed FP32 classes), 8 + 1 on
-// unscaled sources (FP32 large class, FP64),
+// sources pre-scaled by 1/Gamma (FP32), 8 + 1 on unscaled sources (FP64, and
+// the large FP32 class's ragged tails of fewer than 32 targets),
 // no MFMA (the sum is not a dense contraction).
 #include <cmath>
 #include <type_traits>
@@ -70,10 +70,11 @@ template <> struct PassAOf<float> { using type = Scl32; };
 template <> struct PassAOf<double> { using type = Src64; };
 
 // Which LDS kernels keep a scaled copy of the wake (16 B more per vortex):
-// the FP32 small class. The FP32 large class reads its wake unscaled: its
-// capacity is what LDS holds, and the copy would send rollouts of 3k-5k
-// vortices to the streamed class, which runs them slower than the unscaled
-// pair costs. The streamed class scales each staged tile.
+// the FP32 small class. The FP32 large class has no copy: its capacity is
+// what LDS holds, and a copy would send rollouts of 3k-5k vortices to the
+// streamed class, which runs them slower; each wave scales its sources in
+// batches per chunk instead (accumulate_staged). The streamed class scales
+// each staged tile.
 template <typename R, int NW> constexpr bool lds_scaled() { return sizeof(R) == 4 && NW == 4; }
 
 template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
@@ -285,6 +286,34 @@ __device__ inline void accumulate(const S *__restrict__ src,
       for (int j = 0; j < T; ++j) pair_term(tx[j], tz[j], v, rc4, ax[j], az[j]);
     }
     fold_tile<R, T>(sx, sz, cx, cz, ax, az);
+  }
+}
+
+// All lanes of a wave: its LDS writes are visible to its own later reads.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FP32 large class: the wave's sources [s_lo, s_hi) of the unscaled wake,
+// scaled 32 T at a time into `stage` (the wave's own slot of the chunk's
+// partial-sum buffer, unused until the chunk's sums are written), so the
+// pair costs 8 instructions without a scaled copy of the wake in LDS.
+// Conversion: ~12 instructions per source per chunk, under 1 % of the
+// 8 T per source it buys back for T = 4.
+template <int T, int TILE>
+__device__ inline void accumulate_staged(const Src32 *__restrict__ src, Scl32 *stage, int s_lo,
+                                         int s_hi, float rc, int lane, const float (&tx)[T],
+                                         const float (&tz)[T], float (&sx)[T], float (&sz)[T],
+                                         float (&cx)[T], float (&cz)[T]) {
+  constexpr int kStage = 32 * T;  // 64 T float2 of partial sums = 32 T Scl32
+  for (int b0 = s_lo; b0 < s_hi; b0 += kStage) {
+    const int cnt = min(kStage, s_hi - b0);
+    for (int q = lane; q < cnt; q += 64) stage[q] = pass_a_source(src[b0 + q], rc);
+    wave_lds_sync();
+    accumulate<float, T, TILE>(stage, 0, cnt, tx, tz, 0.0f, sx, sz, cx, cz);
+    wave_lds_sync();  // every lane done with the batch before it is overwritten
   }
 }
 
@@ -869,7 +898,11 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
     target_pos(a, sh, src, c0 + lane + 64 * j, NT, head, tx[j], tz[j]);
     sx[j] = sz[j] = cx[j] = cz[j] = R(0);
   }
-  accumulate<R, T, TILE>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
+  if constexpr (std::is_same_v<S, Src32>)
+    accumulate_staged<T, TILE>(pa, reinterpret_cast<Scl32 *>(red + wave * 64 * T), s_lo, s_hi,
+                               rc, lane, tx, tz, sx, sz, cx, cz);
+  else
+    accumulate<R, T, TILE>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
   Vec2<R> *out = red + wave * 64 * T;
 #pragma unroll
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
@@ -1008,7 +1041,12 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
           if (tt < n_surf) {
             vsurf[tt] = make_double2(vx, vz);
           } else {
-            vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};  // self term: pass B
+            const int i = head + tt - n_surf;
+            // the self term of a scaled pair: the small class removes it in
+            // pass B; staged chunks of the large class here (tails are unscaled)
+            if constexpr (sizeof(R) == 4 && !SCL)
+              if (!tail) remove_self(src[i].x, src[i].z, pass_a_source(src[i], float(a.r_core)), vx, vz);
+            vel[i] = Vec2<R>{R(vx), R(vz)};
           }
         }
         __syncthreads();
@@ -1236,6 +1274,7 @@ int lds_layout(int cap, int nb, int tmax, KArgs &a) {
   off = (off + 15) & ~size_t(15);
   a.off_kinv = static_cast<int>(off);
   off += (size_t)a.n_inv * sizeof(double);
+  off = (off + 15) & ~size_t(15);  // 16-byte records follow
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = static_cast<int>(off);
@@ -1251,6 +1290,7 @@ int stream_layout(int nb, KArgs &a) {
   a.off_scl = 0;
   a.off_kinv = static_cast<int>(off);
   off += (size_t)a.n_inv * sizeof(double);
+  off = (off + 15) & ~size_t(15);  // 16-byte records follow
   a.off_vsurf = static_cast<int>(off);
   off += (size_t)(2 * nb + 3) * sizeof(double2);
   a.off_red = a.off_vel = 0;
