@@ -198,7 +198,8 @@ __device__ inline void pair_term(double tx, double tz, const Src64 &v, double rc
 // itself vanish, but in scaled form dx' = fma(x, q, -RN(q x)) is the rounding
 // error of q x, not 0: the self term is of order g |x| 2^-24 / rc^2. It is
 // recomputed with the same operations and taken out of the vortex's velocity
-// (the streamed class at the end of pass A, the LDS small class in pass B).
+// (the streamed class at the end of pass A, the large LDS class in the
+// cross-wave combine, the small LDS class in pass B).
 __device__ inline void remove_self(float x, float z, const Scl32 &v, double &vx, double &vz) {
   float ax = 0.0f, az = 0.0f;
   reg_term_scaled(x, z, v, ax, az);
@@ -212,7 +213,7 @@ __device__ inline void remove_self(float x, float z, const Scl32 &v, double &vx,
 // pass-A source this step (vortices shed this step were not), and q and cs
 // of its decayed strength g_new for the rewritten entry.
 struct Upkeep {
-  double sx, sz;  // self term to take out of the velocity
+  double sx, sz;  // the self term, negated: added to the velocity
   float q, cs;
 };
 template <typename S>
@@ -233,7 +234,7 @@ __device__ inline Scl32 pass_a_source(const Src32 &s, float rc) {
 }
 __device__ inline Src64 pass_a_source(const Src64 &s, double) { return s; }
 
-// Keep entry p of the scaled copy (FP32 LDS kernels; null otherwise) in step
+// Keep entry p of the scaled copy (FP32 small class; null otherwise) in step
 // with the wake entry s just written.
 template <typename S>
 __device__ inline void rescale(Scl32 *scl, int p, const S &s, float rc) {
