@@ -1013,8 +1013,11 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       const int s_hi = head + (n_w * (wave + 1)) / NW;
       for (int c0 = 0; c0 < NT;) {
         const int rem = NT - c0;
-        int T = TMAX;  // largest chunk that is full; a tail below 64 takes T=1
-        while (T > 1 && 64 * T > rem) T >>= 1;
+        // largest chunk at least 3/4 full (fewer chunks, barriers and
+        // cross-wave combines for a few idle target slots); a tail below 64
+        // takes T=1
+        int T = TMAX;
+        while (T > 1 && 48 * T > rem) T >>= 1;
         const int tail = rem < 32 ? rem : 0;  // tails of 32..63 keep a lane each
         if (tail) {
           lds_pass_a_tail<R, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
