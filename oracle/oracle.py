@@ -46,7 +46,7 @@ class Params(C.Structure):
         ("s_elev", C.c_double),
         ("alpha_crit", C.c_double),
         ("gate", C.c_int32),
-        ("pad_", C.c_int32),
+        ("lev_literal", C.c_int32),
     ]
 
 
@@ -116,8 +116,8 @@ def _f64(a):
 def make_params(d: dict) -> Params:
     p = Params()
     for name, _ in Params._fields_:
-        if name != "pad_":
-            setattr(p, name, d.get(name, 0) if name in ("gate", "alpha_crit") else d[name])
+        optional = name in ("gate", "alpha_crit", "lev_literal")
+        setattr(p, name, d.get(name, 0) if optional else d[name])
     return p
 
 

@@ -420,6 +420,7 @@ int32_t orc_segment_hits_plate(const orc_params *p, const double *g,
 typedef struct {
   double g[7];
   double *gb_prev;  /* bound circulations of the previous step           */
+  double glev_prev; /* LEV strength of the previous step (lev_literal)   */
   int32_t n_w, cap;
   double *wx, *wz, *wg; /* wake FIFO, index 0 is the oldest                 */
   int32_t *tag;         /* disturbance pair id (q + 1) or 0                   */
@@ -563,8 +564,8 @@ static void orc_step(const orc_params *p, orc_state *s, double dt, double u,
     pre += gb[j];
     pre_prev += s->gb_prev[j];
     double q = vt_b[2 * j] * et[0] + vt_b[2 * j + 1] * et[1];
-    double dp = p->rho * ((gb[j] / lb) * q + (pre - pre_prev) / dt +
-                          glev / dt);
+    double lev_rate = p->lev_literal ? (glev - s->glev_prev) / dt : glev / dt;
+    double dp = p->rho * ((gb[j] / lb) * q + (pre - pre_prev) / dt + lev_rate);
     double arm = (rb[2 * j] - xw[0]) * cos(g[2]) +
                  (rb[2 * j + 1] - xw[1]) * sin(g[2]);
     sum_dp += dp;
@@ -670,6 +671,7 @@ static void orc_step(const orc_params *p, orc_state *s, double dt, double u,
   for (int32_t i = 0; i < 7; ++i) g[i] = (float)g[i];
 #endif
   for (int32_t j = 0; j < nb; ++j) s->gb_prev[j] = gb[j];
+  s->glev_prev = glev;
 
   free(rc);
   free(rb);
@@ -720,6 +722,7 @@ int32_t orc_rollout_batch(
     memcpy(s.g, &g0[7 * k], sizeof(s.g));
     s.gb_prev = (double *)malloc(sizeof(double) * nb);
     memcpy(s.gb_prev, &gb0[(int64_t)nb * k], sizeof(double) * nb);
+    s.glev_prev = 0.0;
     s.n_w = n0;
     s.cap = n0 + shed_per_step(p->shed_mode) * H;
     s.wx = (double *)malloc(sizeof(double) * (s.cap + 1));

@@ -51,7 +51,12 @@ typedef struct {
   double alpha_crit;   /* separation gate threshold on the wing AoA [rad]   */
   int32_t gate;        /* 1: shed both edges only while alpha_w > alpha_crit,
                           the trailing edge alone otherwise (shed_mode BOTH) */
-  int32_t pad_;
+  int32_t lev_literal; /* test switch for the LEV term of Eq. 13: 0 (the
+                          reading used everywhere) takes dGamma_LEV/dt as the
+                          rate Gamma_LEV / dt at which circulation leaves the
+                          leading edge; 1 takes the literal backward
+                          difference of successive LEV strengths, so that a
+                          test can tell the two readings apart              */
 } orc_params;
 
 /* Wing angle of attack (the separation criterion of Sec. III-A, measured
