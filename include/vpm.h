@@ -293,10 +293,21 @@ typedef struct {
   int32_t iterations;       /* MPPI iterations, >= 1: iteration i rolls out
                                the same initial state with the mean updated by
                                iteration i - 1 (the planner's replan runs 3) */
+  int32_t advance;          /* 0..H: after the last iteration, carry the
+                               resident state `advance` steps forward under the
+                               updated controls (no perturbation) and keep
+                               the result as a new resident state (the
+                               receding-horizon step of Sec. IV-C); 0: none  */
   double x_goal[7];         /* cost goal (Eq. 24)                            */
   double q_diag[7];         /* cost weights (Eq. 24)                         */
   const double *u_mean;     /* host [H]: copied at submit                    */
-  const double *u_eps;      /* host [iterations][K][H]: copied at submit     */
+  const double *u_eps;      /* host [iterations][K][H]: copied at submit; or
+                               NULL: drawn at submit from `seed` as
+                               vpm_sample_eps(seed, i, K, H, sigma) for
+                               iteration i                                   */
+  uint64_t seed;            /* with u_eps NULL                               */
+  double sigma;             /* with u_eps NULL: perturbation standard
+                               deviation (>= 0, the control's units)         */
 } plan_req;
 
 typedef struct {
@@ -308,17 +319,39 @@ typedef struct {
   double *w;                /* host [K] weights of the last iteration, or NULL */
   double *cost;             /* host [K] costs of the last iteration, or NULL  */
   double *g_final;          /* host [K][7] caller buffer, or NULL            */
-  double t_arrive_us;       /* submit time (us since planner_create)        */
+  double t_arrive_us;       /* submit time (us since planner_create), taken on
+                               entry to planner_submit                       */
   double t_admit_us;        /* admission time                               */
   double t_done_us;         /* completion time (results in host memory)     */
   int64_t pairs;            /* pair-interactions of the request (all
-                               iterations)                                   */
+                               iterations; the advance not included)         */
+  uint64_t new_state_id;    /* the advanced resident state (advance > 0 and
+                               status VPM_OK), else 0; the caller drops it   */
+  int32_t new_state_status; /* VPM_ROLLOUT_* bits of the advance rollout     */
+  int32_t reserved;
 } plan_result;
 
 /* Create / destroy a planner (it owns one context and stream per slot).
- * planner_destroy waits for in-flight requests. */
+ * planner_destroy waits for in-flight requests. The HBM budget lives in
+ * planner_opts rather than in vpm_create because admission is the planner's
+ * job: a bare context allocates only what the calls made on it need. */
 VPM_API int planner_create(planner **out, const planner_opts *opts);
 VPM_API void planner_destroy(planner *p);
+
+/* Size every slot (staging, per-rollout buffers, plate inverses, rollout
+ * workspaces) for requests of up to K rollouts, H steps, resident wakes of
+ * n0 vortices and `iterations` iterations with these params, so that serving
+ * such requests allocates and frees no device memory (a growth while other
+ * slots run would synchronise the device and serialise them). Not a step of
+ * the method: a set-up call. Needs an idle planner (nothing queued or
+ * running). Errors: VPM_EINVAL (bad sizes, busy planner), VPM_ENOMEM,
+ * VPM_ESINGULAR, VPM_EDEVICE. */
+VPM_API int planner_reserve(planner *p, const vpm_params *params, int32_t K, int32_t H,
+                            int32_t n0, int32_t iterations);
+
+/* vpm_set_tuning for the kernel class on every slot's context. */
+VPM_API int planner_set_tuning(planner *p, int32_t kernel_class, int32_t targets_per_thread,
+                               int32_t tile);
 
 /* Upload a fluid and vehicle state and keep it resident: n vortices (host
  * arrays, age order), glider state g7 (host [7]) and previous bound
@@ -327,11 +360,18 @@ VPM_API int planner_state_put(planner *p, int32_t n, const double *wx,
                               const double *wz, const double *wg,
                               const double *g7, int32_t n_bound,
                               const double *gb, uint64_t *state_id);
+/* Read a resident state back: *n (its wake count) always; the wake (host
+ * arrays of `capacity` >= n entries), g7 [7] and gb [n_bound] for each
+ * pointer that is not NULL. Errors: VPM_EINVAL, VPM_ENOTFOUND, VPM_EDEVICE. */
+VPM_API int planner_state_get(planner *p, uint64_t state_id, int32_t *n, double *wx,
+                              double *wz, double *wg, double *g7, double *gb,
+                              int32_t capacity);
 VPM_API int planner_state_drop(planner *p, uint64_t state_id);
 
-/* Queue a request; its inputs are copied, so the caller may reuse them on
- * return. Returns a ticket. Errors: VPM_EINVAL, VPM_ENOTFOUND (state),
- * VPM_EBUDGET (the request alone exceeds the budget). */
+/* Queue a request; its inputs are copied (seeded perturbations are drawn
+ * here, on the caller's thread), so the caller may reuse them on return.
+ * Returns a ticket. Errors: VPM_EINVAL, VPM_ENOTFOUND (state), VPM_EBUDGET
+ * (the request alone exceeds the budget). */
 VPM_API int planner_submit(planner *p, const plan_req *req, uint64_t *ticket);
 
 /* Wait up to timeout_us (0: do not wait, < 0: forever) for a request.
@@ -341,10 +381,26 @@ VPM_API int planner_poll(planner *p, uint64_t ticket, plan_result *res,
                          int32_t timeout_us);
 
 /* Device-memory footprint the planner charges a request against its budget
- * (host arithmetic): inputs (perturbations of every iteration), outputs and,
- * for wakes beyond the LDS-resident kernel, the streaming workspace. */
-VPM_API size_t planner_footprint(int32_t K, int32_t H, int32_t n0,
-                                 int32_t n_bound, int32_t iterations);
+ * (host arithmetic): perturbations of every iteration, per-rollout inputs
+ * and outputs, the advanced state, and for wakes beyond the LDS-resident
+ * kernel in params' precision the streaming workspace of one slot per CU.
+ * Returns 0 for NULL params or n_bound outside 1..64. */
+VPM_API size_t planner_footprint(const vpm_params *params, int32_t K, int32_t H, int32_t n0,
+                                 int32_t iterations, int32_t advance);
+
+/* MPPI control perturbations from a seed (Sec. IV-A: the K sampled control
+ * sequences around the mean), host FP64: out [K][H] (host) receives sigma * z
+ * for rollouts k = 0..K-1, steps n = 0..H-1 of MPPI iteration `iteration`,
+ * z standard normal from Philox4x64-10 (Salmon et al., SC 2011; key
+ * (seed, 0), counter (n / 4, k, iteration, 0)) and the Box-Muller transform
+ * of its output words taken in pairs (w0, w1) for steps 4j, 4j+1 and
+ * (w2, w3) for 4j+2, 4j+3: with u_a = ((w_a >> 11) + 1) 2^-53 and
+ * u_b = (w_b >> 11) 2^-53, r = sqrt(-2 ln u_a), t = 2 pi u_b, the pair is
+ * (r cos t, r sin t). Each value depends on (seed, iteration, k, n) only.
+ * Errors: VPM_EINVAL (K or H < 1, iteration < 0, sigma < 0 or not finite,
+ * out NULL). */
+VPM_API int vpm_sample_eps(uint64_t seed, int32_t iteration, int32_t K, int32_t H,
+                           double sigma, double *out);
 
 /* Local feedback policy from rollouts (Sec. IV-B). Least-squares Jacobians
  * at every step (Eqs. 26-28): the rates of the K perturbed rollouts minus

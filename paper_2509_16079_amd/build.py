@@ -13,8 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvpm.so")
-SOURCES = ["api.hip", "plate_system.cpp", "rollout.hip", "solve_mppi.hip", "planner.hip",
-           "policy.hip", "replan.hip"]
+SOURCES = ["host.cpp", "sampling.cpp", "plate_system.cpp", "api.hip", "rollout.hip",
+           "solve_mppi.hip", "planner.hip", "policy.hip", "replan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -31,8 +31,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        # .cpp sources are host-only C++ (no device code)
+        cmd = [HIPCC] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -1,5 +1,6 @@
-// api.hip -- the C ABI declared in include/vpm.h: argument validation (pure
-// host code, runs before any HIP call), context management and dispatch.
+// api.hip -- the C ABI declared in include/vpm.h: context management, the
+// device copy of the plate inverse and dispatch (argument checks are in
+// host.cpp).
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -8,48 +9,37 @@
 
 namespace vpm {
 
-static thread_local std::string g_error;
-
-void set_error(const std::string &msg) { g_error = msg; }
-int fail(int code, const std::string &msg) {
-  g_error = msg;
-  return code;
-}
-
-namespace {
-
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-int check_params(const vpm_params *p) {
-  if (!p) return fail(VPM_EINVAL, "params is NULL");
-  if (p->n_bound < 1 || p->n_bound > kMaxBound)
-    return fail(VPM_EINVAL, "n_bound must be in 1..64");
-  if (p->shed_mode < VPM_SHED_BOTH || p->shed_mode > VPM_SHED_NONE)
-    return fail(VPM_EINVAL, "unknown shed_mode");
-  if (p->precision != VPM_FP32C && p->precision != VPM_FP64)
-    return fail(VPM_EINVAL, "unknown precision");
-  if (!finite_pos(p->chord)) return fail(VPM_EINVAL, "chord must be > 0");
-  if (!(std::isfinite(p->shed_frac) && p->shed_frac >= 0.0))
-    return fail(VPM_EINVAL, "shed_frac must be >= 0");
-  if (!(std::isfinite(p->r_core) && p->r_core >= 1e-6))
-    return fail(VPM_EINVAL, "r_core must be >= 1e-6 m");
-  if (!(std::isfinite(p->decay) && p->decay >= 0.0))
-    return fail(VPM_EINVAL, "decay must be >= 0");
-  if (!finite_pos(p->mass) || !finite_pos(p->inertia))
-    return fail(VPM_EINVAL, "mass and inertia must be > 0");
-  const double f[] = {p->rho, p->span, p->grav, p->l_body, p->l_wing,
-                      p->l_elev, p->s_elev};
-  for (double v : f)
-    if (!std::isfinite(v)) return fail(VPM_EINVAL, "non-finite parameter");
-  if (p->gate != 0 && p->gate != 1) return fail(VPM_EINVAL, "gate must be 0 or 1");
-  if (p->gate && (p->shed_mode != VPM_SHED_BOTH || !std::isfinite(p->alpha_crit)))
-    return fail(VPM_EINVAL, "the separation gate needs shed_mode BOTH and a finite alpha_crit");
-  if (p->shed_mode == VPM_SHED_NONE && p->n_bound < 2)
-    return fail(VPM_EINVAL, "shed_mode NONE needs n_bound >= 2");
+int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
+                         const double **out, bool capturing) {
+  PlateKey key{p->n_bound, mode, p->chord, p->shed_frac, p->r_core};
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  auto it = ctx->plate_cache.find(key);
+  if (it != ctx->plate_cache.end()) {
+    *out = it->second;
+    return VPM_OK;
+  }
+  if (capturing)
+    return fail(VPM_EINVAL, "the plate inverse of this geometry must be built by an "
+                            "eager call before graph capture");
+  std::vector<double> inv_t;
+  int rc = plate_inverse_T(p->n_bound, p->chord, p->shed_frac, p->r_core, mode,
+                           inv_t);
+  if (rc != VPM_OK) return fail(rc, "plate system is singular");
+  double *d = nullptr;
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  if (hipMalloc(&d, inv_t.size() * sizeof(double)) != hipSuccess)
+    return fail(VPM_ENOMEM, "hipMalloc of the plate inverse failed");
+  hipError_t e = hipMemcpy(d, inv_t.data(), inv_t.size() * sizeof(double),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return fail(VPM_EDEVICE, std::string("plate inverse upload: ") +
+                                 hipGetErrorString(e));
+  }
+  ctx->plate_cache[key] = d;
+  *out = d;
   return VPM_OK;
 }
-
-}  // namespace
 
 bool stream_capturing(hipStream_t stream) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -61,41 +51,6 @@ bool stream_capturing(hipStream_t stream) {
 using vpm::fail;
 
 extern "C" {
-
-VPM_API const char *vpm_last_error(void) { return vpm::g_error.c_str(); }
-
-VPM_API int vpm_validate_batch(const vpm_params *p, const vpm_batch_in *in,
-                               const vpm_batch_out *out) {
-  int rc = vpm::check_params(p);
-  if (rc != VPM_OK) return rc;
-  if (!in || !out) return fail(VPM_EINVAL, "in or out is NULL");
-  if (in->K < 1 || in->H < 1) return fail(VPM_EINVAL, "K and H must be >= 1");
-  if (!vpm::finite_pos(in->dt)) return fail(VPM_EINVAL, "dt must be > 0");
-  if (in->n_fields < 1) return fail(VPM_EINVAL, "n_fields must be >= 1");
-  if (in->max_wake0 < 0) return fail(VPM_EINVAL, "max_wake0 must be >= 0");
-  if ((long long)in->max_wake0 + 2LL * in->H > (1LL << 30))
-    return fail(VPM_EINVAL, "max_wake0 + 2H too large");
-  if (in->n_pairs < 0 || in->n_pairs > vpm::kMaxPairs)
-    return fail(VPM_EINVAL, "n_pairs must be in 0..4");
-  if (in->n_pairs > 0 && !in->pairs)
-    return fail(VPM_EINVAL, "pairs is NULL with n_pairs > 0");
-  if (!in->g0 || !in->gb0 || !in->field_off || !in->wx || !in->wz ||
-      !in->wg || !in->u_mean || !in->u_eps)
-    return fail(VPM_EINVAL, "a required input pointer is NULL");
-  if (!in->field_of && in->n_fields < in->K)
-    return fail(VPM_EINVAL, "field_of is NULL but n_fields < K");
-  if ((in->fb_gain == nullptr) != (in->fb_xref == nullptr))
-    return fail(VPM_EINVAL, "fb_gain and fb_xref go together");
-  for (int i = 0; i < 7; ++i)
-    if (!std::isfinite(in->x_goal[i]) || !std::isfinite(in->q_diag[i]))
-      return fail(VPM_EINVAL, "non-finite x_goal or q_diag");
-  if (!out->g_final || !out->cost || !out->status)
-    return fail(VPM_EINVAL, "g_final, cost and status are required");
-  const bool any_wake = out->wx || out->wz || out->wg || out->vel_last;
-  if (any_wake && (!out->wake_off || !out->n_final))
-    return fail(VPM_EINVAL, "wake outputs need wake_off and n_final");
-  return VPM_OK;
-}
 
 VPM_API int vpm_create(vpm_ctx **out, int device) {
   if (!out) return fail(VPM_EINVAL, "out is NULL");
@@ -119,12 +74,12 @@ VPM_API int vpm_create(vpm_ctx **out, int device) {
   (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device);
   c->max_lds = lds > optin ? lds : optin;
   if (c->max_lds <= 0) c->max_lds = 65536;
+  // the side streams of uneven batches are created on first use: a context
+  // that never runs one (as each planner slot's) holds no idle streams, which
+  // would otherwise share the process's hardware queues with busy ones
   bool ok = hipSetDevice(device) == hipSuccess &&
             hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&c->fork_event, hipEventDisableTiming) == hipSuccess;
-  for (int i = 0; i < 3 && ok; ++i)
-    ok = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&c->join_event[i], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     vpm_destroy(c);
     return fail(VPM_EDEVICE, "stream or event creation failed");
@@ -303,18 +258,6 @@ VPM_API int vpm_fd_jacobians(vpm_ctx *ctx, const vpm_params *params, const vpm_f
   if (rc == VPM_OK) rc = vpm::check_fd(params, in, out);
   if (rc != VPM_OK) return rc;
   return vpm::run_fd(ctx, params, in, out, static_cast<hipStream_t>(stream));
-}
-
-VPM_API int64_t vpm_pair_count(int32_t n0, int32_t H, int32_t n_bound,
-                               int32_t n_wake_max) {
-  int64_t total = 0, n = n0;
-  for (int32_t s = 0; s < H; ++s) {
-    const int64_t m = n + 2;
-    total += n * (2 * n_bound + 1) + m * (m - 1) + m * n_bound;
-    n = m;
-    if (n_wake_max > 0 && n > n_wake_max) n = n_wake_max;
-  }
-  return total;
 }
 
 }  // extern "C"

@@ -8,9 +8,10 @@
 // in the plate's own frame and inverted once per geometry, after which each
 // step's solve (Eq. 11) is one FP64 matrix-vector product.
 #include <cmath>
+#include <utility>
 #include <vector>
 
-#include "vpm_internal.h"
+#include "host_common.h"
 
 namespace vpm {
 
@@ -84,38 +85,6 @@ int plate_inverse_T(int nb, double chord, double shed_frac, double r_core,
   inv_t.assign(static_cast<size_t>(S) * S, 0.0);
   for (int i = 0; i < S; ++i)
     for (int j = 0; j < S; ++j) inv_t[j * S + i] = inv[i * S + j];
-  return VPM_OK;
-}
-
-int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
-                         const double **out, bool capturing) {
-  PlateKey key{p->n_bound, mode, p->chord, p->shed_frac, p->r_core};
-  std::lock_guard<std::mutex> lock(ctx->mu);
-  auto it = ctx->plate_cache.find(key);
-  if (it != ctx->plate_cache.end()) {
-    *out = it->second;
-    return VPM_OK;
-  }
-  if (capturing)
-    return fail(VPM_EINVAL, "the plate inverse of this geometry must be built by an "
-                            "eager call before graph capture");
-  std::vector<double> inv_t;
-  int rc = plate_inverse_T(p->n_bound, p->chord, p->shed_frac, p->r_core, mode,
-                           inv_t);
-  if (rc != VPM_OK) return fail(rc, "plate system is singular");
-  double *d = nullptr;
-  VPM_HIP_TRY(hipSetDevice(ctx->device));
-  if (hipMalloc(&d, inv_t.size() * sizeof(double)) != hipSuccess)
-    return fail(VPM_ENOMEM, "hipMalloc of the plate inverse failed");
-  hipError_t e = hipMemcpy(d, inv_t.data(), inv_t.size() * sizeof(double),
-                           hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(d);
-    return fail(VPM_EDEVICE, std::string("plate inverse upload: ") +
-                                 hipGetErrorString(e));
-  }
-  ctx->plate_cache[key] = d;
-  *out = d;
   return VPM_OK;
 }
 

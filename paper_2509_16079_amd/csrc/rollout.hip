@@ -1453,10 +1453,12 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 
   // uneven batch: plan, then the class kernels
   std::lock_guard<std::mutex> lock(ctx->ws_mu);
+  int rc = ensure_side_streams(ctx, capturing);
+  if (rc != VPM_OK) return rc;
   if (ctx->ws_event_valid && !capturing)
     VPM_HIP_TRY(hipStreamWaitEvent(stream, ctx->ws_event, 0));
   const size_t plan_bytes = (size_t)a.K * sizeof(int32_t) + 64;
-  int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan", capturing);
+  rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan", capturing);
   if (rc != VPM_OK) return rc;
   int2 *range = static_cast<int2 *>(ctx->plan);
   int32_t *next = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->plan) + 32);
@@ -1512,6 +1514,19 @@ int run_batch(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream) {
 
 }  // namespace
 
+int ensure_side_streams(vpm_ctx *ctx, bool capturing) {
+  if (ctx->side[2]) return VPM_OK;
+  if (capturing)
+    return fail(VPM_EINVAL, "an eager uneven batch must run on this context before graph "
+                            "capture");
+  for (int i = 0; i < 3; ++i) {
+    if (!ctx->side[i]) VPM_HIP_TRY(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+    if (!ctx->join_event[i])
+      VPM_HIP_TRY(hipEventCreateWithFlags(&ctx->join_event[i], hipEventDisableTiming));
+  }
+  return VPM_OK;
+}
+
 // Grow a context buffer to `bytes` (device-synchronises before freeing a
 // smaller one). Under graph capture nothing may be allocated: the buffer must
 // already have been grown by an eager call of the same shape.
@@ -1553,7 +1568,8 @@ int reserve_batch(vpm_ctx *ctx, int nb, int n_inv, int K, int cap, int n_fields)
   }
   if (path == VPM_PATH_AUTO && n_fields > 1) {
     const size_t plan_bytes = (size_t)K * sizeof(int32_t) + 64;
-    const int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan", false);
+    int rc = ensure_buffer(&ctx->plan, &ctx->plan_bytes, plan_bytes, "batch plan", false);
+    if (rc == VPM_OK) rc = ensure_side_streams(ctx, false);
     if (rc != VPM_OK) return rc;
   }
   return VPM_OK;
@@ -1568,8 +1584,10 @@ int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wak
   return reserve_batch<float>(ctx, p->n_bound, n_inv, K, cap, n_fields);
 }
 
-int lds_resident_capacity(int nb) {
-  return lds_capacity<float, 16>(nb, (nb + 2) * (nb + 2), 2, 163840);
+int lds_resident_capacity(int nb, int precision) {
+  const int n_inv = (nb + 2) * (nb + 2);
+  return precision == VPM_FP64 ? lds_capacity<double, 8>(nb, n_inv, 2, 163840)
+                               : lds_capacity<float, 16>(nb, n_inv, 2, 163840);
 }
 
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,

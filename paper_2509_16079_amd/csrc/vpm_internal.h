@@ -10,13 +10,10 @@
 #include <tuple>
 #include <vector>
 
+#include "host_common.h"
 #include "vpm.h"
 
 namespace vpm {
-
-// Per-thread error message and a helper that records it.
-void set_error(const std::string &msg);
-int fail(int code, const std::string &msg);
 
 #define VPM_HIP_TRY(expr)                                                   \
   do {                                                                      \
@@ -25,23 +22,6 @@ int fail(int code, const std::string &msg);
       return ::vpm::fail(VPM_EDEVICE, std::string(#expr ": ") +             \
                                           hipGetErrorString(_e));           \
   } while (0)
-
-constexpr int kMaxPairs = 4;
-constexpr int kMaxBound = 64;
-
-// System size per shedding mode (bound unknowns, then LEV, then TEV).
-__host__ __device__ inline int system_size(int nb, int mode) {
-  return mode == VPM_SHED_BOTH ? nb + 2 : mode == VPM_SHED_TE ? nb + 1 : nb;
-}
-// First collocation row of the system per mode (LE row dropped unless BOTH).
-__host__ __device__ inline int first_row(int mode) { return mode == VPM_SHED_BOTH ? 0 : 1; }
-
-// Host FP64: inverse of the surface matrix in the plate's body frame,
-// returned transposed (column j of the inverse is contiguous) so that lane
-// i of a wave reading entry (i, j) touches consecutive addresses.
-// Returns VPM_OK or VPM_ESINGULAR.
-int plate_inverse_T(int nb, double chord, double shed_frac, double r_core,
-                    int mode, std::vector<double> &inv_t);
 
 // FP32 kernel shape of one class: targets per thread (pass-A register
 // blocking) and sources per compensated tile.
@@ -101,9 +81,15 @@ int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
 // True if `stream` is being captured into a graph.
 bool stream_capturing(hipStream_t stream);
 
-// Largest FP32 wake capacity (N_0 + 2H) the LDS-resident kernel holds on a
-// gfx950 workgroup (160 KB of LDS); larger wakes take the streaming kernel.
-int lds_resident_capacity(int nb);
+// Largest wake capacity (N_0 + 2H) the LDS-resident kernel holds on a gfx950
+// workgroup (160 KB of LDS) in a precision (VPM_FP32C or VPM_FP64, with the
+// large class's default 2 targets per thread); larger wakes take the
+// streaming kernel.
+int lds_resident_capacity(int nb, int precision);
+
+// Create the context's side streams for the class kernels of uneven batches
+// (on first use, so that contexts that never run one hold no idle streams).
+int ensure_side_streams(vpm_ctx *ctx, bool capturing);
 
 // Grow the context's workspace and plan buffers for later batches of these
 // sizes (vpm_reserve).

@@ -251,15 +251,18 @@ class DeviceOutputs:
                 self.n_vel_last = torch.empty(K, dtype=torch.int32, device=device)
 
     def batch_out(self, k0=0, k1=None) -> BatchOut:
-        """The ABI output struct for rollouts [k0, k1) (per-rollout arrays
-        only; the wake block is passed for whole batches)."""
+        """The ABI output struct for rollouts [k0, k1) (per-rollout arrays,
+        trajectories and surface circulations included; the wake block is
+        passed for whole batches only)."""
         o = BatchOut()
         if k0 == 0 and k1 is None:
             for name, _ in BatchOut._fields_:
                 setattr(o, name, _ptr(getattr(self, name)))
             return o
         per = dict(g_final=7, cost=1, status=1, pair_count=1, gb_final=self.gb_final.shape[1]
-                   if self.gb_final is not None else 0)
+                   if self.gb_final is not None else 0,
+                   traj=self.traj[0].numel() if self.traj is not None else 0,
+                   gamma_s=self.gamma_s[0].numel() if self.gamma_s is not None else 0)
         for name, width in per.items():
             setattr(o, name, _ptr(getattr(self, name), width * k0))
         return o
@@ -474,14 +477,16 @@ class PlannerOpts(C.Structure):
 
 class PlanReq(C.Structure):
     _fields_ = [("state_id", C.c_uint64), ("params", Params), ("K", _I), ("H", _I), ("dt", _D),
-                ("lam", _D), ("iterations", _I), ("x_goal", _D * 7), ("q_diag", _D * 7),
-                ("u_mean", _P), ("u_eps", _P)]
+                ("lam", _D), ("iterations", _I), ("advance", _I), ("x_goal", _D * 7),
+                ("q_diag", _D * 7), ("u_mean", _P), ("u_eps", _P), ("seed", C.c_uint64),
+                ("sigma", _D)]
 
 
 class PlanResult(C.Structure):
     _fields_ = [("status", _I), ("argmin", _I), ("jmin", _D), ("u_new", _P), ("w", _P),
                 ("cost", _P), ("g_final", _P), ("t_arrive_us", _D), ("t_admit_us", _D),
-                ("t_done_us", _D), ("pairs", C.c_int64)]
+                ("t_done_us", _D), ("pairs", C.c_int64), ("new_state_id", C.c_uint64),
+                ("new_state_status", _I), ("reserved", _I)]
 
 
 def _planner_lib():
@@ -490,19 +495,33 @@ def _planner_lib():
         L.planner_create.argtypes = [C.POINTER(_P), C.POINTER(PlannerOpts)]
         L.planner_destroy.argtypes = [_P]
         L.planner_destroy.restype = None
+        L.planner_reserve.argtypes = [_P, C.POINTER(Params), _I, _I, _I, _I]
+        L.planner_set_tuning.argtypes = [_P, _I, _I, _I]
         L.planner_state_put.argtypes = [_P, _I, _P, _P, _P, _P, _I, _P, C.POINTER(C.c_uint64)]
+        L.planner_state_get.argtypes = [_P, C.c_uint64, C.POINTER(_I), _P, _P, _P, _P, _P, _I]
         L.planner_state_drop.argtypes = [_P, C.c_uint64]
         L.planner_submit.argtypes = [_P, C.POINTER(PlanReq), C.POINTER(C.c_uint64)]
         L.planner_poll.argtypes = [_P, C.c_uint64, C.POINTER(PlanResult), _I]
-        L.planner_footprint.argtypes = [_I, _I, _I, _I, _I]
+        L.planner_footprint.argtypes = [C.POINTER(Params), _I, _I, _I, _I, _I]
         L.planner_footprint.restype = C.c_size_t
+        L.vpm_sample_eps.argtypes = [C.c_uint64, _I, _I, _I, _D, _P]
         L._planner_ready = True
     return L
 
 
-def planner_footprint(K, H, n0, n_bound, iterations=1):
-    return int(_planner_lib().planner_footprint(int(K), int(H), int(n0), int(n_bound),
-                                                int(iterations)))
+def planner_footprint(params: dict, K, H, n0, iterations=1, advance=0, precision=FP32C):
+    p = make_params(params, precision)
+    return int(_planner_lib().planner_footprint(C.byref(p), int(K), int(H), int(n0),
+                                                int(iterations), int(advance)))
+
+
+def sample_eps(seed, iteration, K, H, sigma):
+    """Seeded MPPI perturbations [K, H] of one iteration (``vpm_sample_eps``,
+    host code of the library)."""
+    out = np.empty((int(K), int(H)), dtype=np.float64)
+    check(_planner_lib().vpm_sample_eps(C.c_uint64(int(seed)), int(iteration), int(K), int(H),
+                                        float(sigma), out.ctypes.data), "vpm_sample_eps")
+    return out
 
 
 class Planner:
@@ -527,6 +546,17 @@ class Planner:
         except Exception:
             pass
 
+    def reserve(self, params: dict, K, H, n0, iterations=1, precision=FP32C):
+        """Size every slot for requests up to these sizes (``planner_reserve``)."""
+        p = make_params(params, precision)
+        check(_planner_lib().planner_reserve(self.h, C.byref(p), int(K), int(H), int(n0),
+                                             int(iterations)), "planner_reserve")
+
+    def set_tuning(self, kernel_class, targets_per_thread, tile):
+        check(_planner_lib().planner_set_tuning(self.h, int(kernel_class),
+                                                int(targets_per_thread), int(tile)),
+              "planner_set_tuning")
+
     def put_state(self, wx, wz, wg, g7, gb):
         f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         wx, wz, wg, g7, gb = f(wx), f(wz), f(wg), f(g7), f(gb)
@@ -536,32 +566,55 @@ class Planner:
                                                gb.size, p(gb), C.byref(sid)), "planner_state_put")
         return sid.value
 
+    def get_state(self, sid, n_bound):
+        """(wx, wz, wg, g7, gb) of a resident state, as numpy arrays."""
+        L = _planner_lib()
+        n = _I()
+        check(L.planner_state_get(self.h, int(sid), C.byref(n), None, None, None, None, None, 0),
+              "planner_state_get")
+        wx, wz, wg = (np.zeros(max(n.value, 1)) for _ in range(3))
+        g7, gb = np.zeros(7), np.zeros(int(n_bound))
+        check(L.planner_state_get(self.h, int(sid), C.byref(n), wx.ctypes.data, wz.ctypes.data,
+                                  wg.ctypes.data, g7.ctypes.data, gb.ctypes.data, wx.size),
+              "planner_state_get")
+        k = n.value
+        return wx[:k], wz[:k], wg[:k], g7, gb
+
     def drop_state(self, sid):
         check(_planner_lib().planner_state_drop(self.h, int(sid)), "planner_state_drop")
 
     def submit(self, sid, params: dict, u_mean, u_eps, dt, lam=1.0, x_goal=None, q_diag=None,
-               precision=FP32C):
-        """Queue one request; ``u_eps`` is [K, H] (one MPPI iteration) or
-        [iterations, K, H]."""
+               precision=FP32C, advance=0, seed=None, sigma=None, K=None, iterations=1):
+        """Queue one request. ``u_eps`` is [K, H] (one MPPI iteration) or
+        [iterations, K, H]; or None with ``seed``, ``sigma``, ``K`` and
+        ``iterations`` for perturbations drawn by the library."""
         u_mean = np.ascontiguousarray(u_mean, dtype=np.float64)
-        u_eps = np.ascontiguousarray(u_eps, dtype=np.float64)
-        if u_eps.ndim == 2:
-            u_eps = u_eps[None]
-        iters, K, H = u_eps.shape
         r = PlanReq()
+        if u_eps is None:
+            if seed is None or sigma is None or K is None:
+                raise ValueError("seeded requests need seed, sigma and K")
+            iters, H = int(iterations), u_mean.size
+            r.u_eps, r.seed, r.sigma = None, int(seed), float(sigma)
+        else:
+            u_eps = np.ascontiguousarray(u_eps, dtype=np.float64)
+            if u_eps.ndim == 2:
+                u_eps = u_eps[None]
+            iters, K, H = u_eps.shape
+            r.u_eps = u_eps.ctypes.data
         r.state_id = int(sid)
         r.params = make_params(params, precision)
-        r.K, r.H, r.dt, r.lam, r.iterations = K, H, float(dt), float(lam), iters
+        r.K, r.H, r.dt, r.lam, r.iterations = int(K), int(H), float(dt), float(lam), int(iters)
+        r.advance = int(advance)
         from . import workloads as W
         xg = W.X_GOAL if x_goal is None else x_goal
         qd = W.Q_POS_PITCH if q_diag is None else q_diag
         for i in range(7):
             r.x_goal[i] = float(xg[i])
             r.q_diag[i] = float(qd[i])
-        r.u_mean, r.u_eps = u_mean.ctypes.data, u_eps.ctypes.data
+        r.u_mean = u_mean.ctypes.data
         t = C.c_uint64()
         check(_planner_lib().planner_submit(self.h, C.byref(r), C.byref(t)), "planner_submit")
-        self._shape[t.value] = (K, H)
+        self._shape[t.value] = (int(K), int(H))
         return t.value
 
     def poll(self, ticket, timeout_us=-1):
@@ -577,5 +630,6 @@ class Planner:
             return None
         self._shape.pop(ticket, None)
         out.update(status=r.status, argmin=r.argmin, jmin=r.jmin, t_arrive_us=r.t_arrive_us,
-                   t_admit_us=r.t_admit_us, t_done_us=r.t_done_us, pairs=r.pairs)
+                   t_admit_us=r.t_admit_us, t_done_us=r.t_done_us, pairs=r.pairs,
+                   new_state_id=r.new_state_id, new_state_status=r.new_state_status)
         return out

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2509_16079_amd", "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libvpm_emu.so")
-FILES = ["api.hip", "rollout.hip", "solve_mppi.hip", "policy.hip", "replan.hip",
-         "plate_system.cpp", "vpm_internal.h", "wave_ops.h"]
+FILES = ["host.cpp", "sampling.cpp", "api.hip", "rollout.hip", "solve_mppi.hip", "policy.hip",
+         "replan.hip", "plate_system.cpp", "host_common.h", "vpm_internal.h", "wave_ops.h"]
 
 
 def build():
