@@ -43,7 +43,10 @@ Workloads (``--workload``):
                       policy; one step = one vpm_replan call
 The default run also replays the first requests of the serving trace through
 the replanning service (8 slots) and through the plain one-at-a-time path,
-reporting p50/p99 latency and rollouts/s for both. Prints one JSON line.
+reporting p50/p99 latency and rollouts/s for both, and times one whole MPPI
+step of the large stress batch (all 8192 rollouts x 150 steps, as 8
+launches of 1024 rollouts) under the ``stress`` key, with its error against
+the FP64 oracle on a 64-rollout subsample. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -82,11 +85,19 @@ def parse():
     ap.add_argument("--graph", choices=["on", "off"], default=None,
                     help="capture one MPPI step (rollout batch + weights) in a HIP graph after "
                          "the warm-up and time its replays (default: on for the uneven batch)")
+    ap.add_argument("--serving-slots", type=int, default=8,
+                    help="concurrent slots of the served replay (default 8)")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests of the serving trace to replay (0: skip)")
     ap.add_argument("--slice", type=int, default=None,
                     help="launch the batch in slices of this many rollouts, reporting each "
                          "finished slice (default: whole batch; 1024 for stress)")
+    ap.add_argument("--stress-record", choices=["on", "off"], default=None,
+                    help="time one full MPPI step of the stress batch after the realtime "
+                         "line (default: on for the realtime workload)")
+    ap.add_argument("--max-k", type=int, default=None,
+                    help="run only the first K rollouts of the workload (profiling runs of "
+                         "one launch)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -134,7 +145,8 @@ def work_counts(wl):
 # dominant kernel per workload (FETCH_SIZE and WRITE_SIZE passes, scaled by a
 # copy-kernel calibration); it is reported only while the kernel source still
 # has the hash recorded beside it.
-TRAFFIC_PROFILE = {"realtime": "profiles/rollout_lds_kernel_realtime_K1024_H200.md"}
+TRAFFIC_PROFILE = {"realtime": "profiles/rollout_lds_kernel_realtime_K1024_H200.md",
+                   "stress": "profiles/rollout_stream_kernel_stress_K8192_H150.md"}
 
 
 def measured_traffic(workload):
@@ -180,8 +192,9 @@ def cpu_baseline(name, wl):
         what = "64 rollouts stratified by initial wake size, full horizon H=100"
     else:
         idx = np.linspace(0, wl.K - 1, 64).astype(np.int64)
-        H = 1
-        what = "64 rollouts (evenly spaced), first step only (1 of 150), per-pair rate"
+        H = STRESS_ORACLE_STEPS
+        what = ("64 rollouts (evenly spaced), first %d of 150 steps, per-pair rate"
+                % STRESS_ORACLE_STEPS)
     sub = wl.subset(idx)
     if H != wl.H:
         from dataclasses import replace
@@ -189,7 +202,9 @@ def cpu_baseline(name, wl):
     t0 = time.perf_counter()
     o = O.rollout_batch(sub.params, sub.K, sub.H, sub.dt, sub.g0, sub.gb0, sub.field_off,
                         sub.field_of, sub.wx, sub.wz, sub.wg, sub.pairs, sub.u, sub.x_goal,
-                        sub.q_diag, final_wake=True, n_threads=threads)
+                        sub.q_diag, final_wake=True, n_threads=threads,
+                        vel_last=name == "stress", gamma_s=name == "stress",
+                        traj=name == "stress")
     dt = time.perf_counter() - t0
     pairs = sum(sum(W.pair_count(int(n), H, sub.params["n_bound"],
                                  n_wake_max=sub.params["n_wake_max"])) for n in sub.n0)
@@ -310,35 +325,48 @@ def error_vs_oracle(V, ctx, sub, o, prec, horizon_note):
     }
 
 
-def serving(n_requests, sweep=False):
+def serving(n_requests, sweep=False, slots=8, tuning=None):
     """Replay the first requests of the serving trace (Poisson arrivals at
     100 req/s, K~U{256..2048}, H~U{50..200}, 16 resident states of
-    500..6000 vortices) through the service and through the plain path.
-    With `sweep`, also replay them at offered loads of 0.25, 0.5 and 0.8 of
-    the capacity measured in the saturated replay (arrival gaps stretched)."""
+    500..6000 vortices, perturbations drawn by the library from each
+    request's seed) through the service with `slots` concurrent slots and
+    through the plain path (the same service with one slot: one request at a
+    time, same kernels). Both are sized up front for the trace's largest
+    request (planner_reserve) and run the tuned kernel shapes. With `sweep`,
+    also replay them at offered loads of 0.25, 0.5 and 0.8 of the capacity
+    measured in the saturated replay (arrival gaps stretched)."""
+    from paper_2509_16079_amd import autotune as A
     from paper_2509_16079_amd import vpm as V
     from paper_2509_16079_amd import workloads as W
     params, states, reqs = W.serving_trace()
     reqs = reqs[:n_requests]
-    eps = [W.request_eps(r) for r in reqs]
     dt = float(W.f32(0.005))
     g0 = np.array([0, 0, 0, 0, 6.0, 0, 0])
+    if tuning is None:
+        tuning = A.DEFAULT_TABLE if os.path.exists(A.DEFAULT_TABLE) else "none"
+    table = A.load(tuning) if tuning != "none" else None
+    k_max, h_max = max(r.K for r in reqs), max(r.H for r in reqs)
+    n_max = max(len(st[0]) for st in states)
 
-    def replay(slots, stretch=1.0):
-        p = V.Planner(max_slots=slots, budget_bytes=64 << 30)
+    def replay(n_slots, stretch=1.0):
+        p = V.Planner(max_slots=n_slots, budget_bytes=64 << 30)
         try:
-            sids = [p.put_state(*s, g0, np.zeros(32)) for s in states]
+            sids = [p.put_state(*st, g0, np.zeros(32)) for st in states]
+            if table is not None:
+                A.apply(p, table)
+            p.reserve(params, K=k_max, H=h_max, n0=n_max)
             # warm-up (not timed): one small request per resident state
             for sid in sids:
                 p.poll(p.submit(sid, params, np.zeros(4), np.zeros((64, 4)), dt))
             t_start = time.perf_counter()
             tickets = []
-            for r, e in zip(reqs, eps):
+            for r in reqs:
                 delay = (t_start + stretch * (r.t_arrive - reqs[0].t_arrive)
                          - time.perf_counter())
                 if delay > 0:
                     time.sleep(delay)
-                tickets.append(p.submit(sids[r.state], params, np.zeros(r.H), e, dt))
+                tickets.append(p.submit(sids[r.state], params, np.zeros(r.H), None, dt,
+                                        seed=r.seed, sigma=0.15, K=r.K))
             res = [p.poll(t) for t in tickets]
         finally:
             p.close()
@@ -347,16 +375,21 @@ def serving(n_requests, sweep=False):
         span = (max(x["t_done_us"] for x in res) - min(x["t_arrive_us"] for x in res)) * 1e-6
         rollouts = sum(r.K for r in reqs)
         pairs = sum(x["pairs"] for x in res)
+        print("serving replay with %d slot(s) done" % n_slots, file=sys.stderr, flush=True)
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "rollouts_per_s": rollouts / span, "pair_interactions_per_s": pairs / span,
                 "makespan_s": span}
 
-    served = replay(8)
+    served = replay(slots)
     plain = replay(1)
     out = {"requests": len(reqs), "trace": "first %d requests of the seeded 100 req/s "
            "trace (K~U{256..2048}, H~U{50..200}, resident states of 500..6000 vortices)"
            % len(reqs),
-           "served_8_slots": served, "plain_one_at_a_time": plain,
+           "latency_sample": "%d requests (p99 interpolated between the two slowest)"
+           % len(reqs),
+           "tuning": os.path.relpath(tuning, ROOT) if tuning != "none" else None,
+           "served_slots": slots,
+           "served": served, "plain_one_at_a_time": plain,
            "p99_speedup": plain["p99_ms"] / served["p99_ms"],
            "rollouts_speedup": served["rollouts_per_s"] / plain["rollouts_per_s"]}
     if sweep:
@@ -368,11 +401,120 @@ def serving(n_requests, sweep=False):
         out["sweep"] = []
         for f in (0.25, 0.5, 0.8):
             stretch = offered / (f * cap)
-            s8, s1 = replay(8, stretch), replay(1, stretch)
-            out["sweep"].append({"load": f, "served_8_slots": s8, "plain_one_at_a_time": s1,
+            s8, s1 = replay(slots, stretch), replay(1, stretch)
+            out["sweep"].append({"load": f, "served": s8, "plain_one_at_a_time": s1,
                                  "p99_speedup": s1["p99_ms"] / s8["p99_ms"]})
             print("serving sweep load %.2f done" % f, file=sys.stderr, flush=True)
     return out
+
+
+STRESS_DESC = ("large stress: K=8192 rollouts, H=150 steps, dt=5 ms, N_b=64, 16376-vortex "
+               "Lamb-Oseen field + 4 pairs, N_w,max=16384")
+
+
+def stress_record(args, with_oracle=True):
+    """One whole MPPI step of the large stress batch, timed once after a
+    256-rollout warm-up launch: 8 launches of 1024 rollouts (HIP events
+    around each, on the launch stream) and the weights over all 8192. Then
+    the GPU path on a 64-rollout subsample (evenly spaced) for the first
+    STRESS_ORACLE_STEPS steps in FP32C and FP64 against the FP64 oracle on
+    the machine's host cores, which also gives the oracle's CPU rate."""
+    import torch
+
+    from paper_2509_16079_amd import vpm as V
+    from paper_2509_16079_amd import workloads as W
+    wl = W.large_stress()
+    ctx = V.Context(0)
+    tuning = apply_tuning(ctx, args.tuning)
+    db = V.DeviceBatch(wl)
+    out = V.DeviceOutputs(db, pair_count=True)
+    stream = torch.cuda.current_stream()
+    n_reg, n_sing = work_counts(wl)
+    slice_k = 1024
+    n_launch = wl.K // slice_k
+    ctx.rollout(wl.params, db, out, V.FP32C, stream, 0, 256)
+    torch.cuda.synchronize()
+    print("stress warm-up done", file=sys.stderr, flush=True)
+    evs = []
+    t0 = time.perf_counter()
+    for k0 in range(0, wl.K, slice_k):
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record(stream)
+        ctx.rollout(wl.params, db, out, V.FP32C, stream, k0, k0 + slice_k)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        evs.append(ev)
+        print("stress launch %d..%d done" % (k0, k0 + slice_k), file=sys.stderr, flush=True)
+    ctx.mppi(out.cost, wl.lam, db.u_mean, db.u_eps, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = n_reg + n_sing
+    assert int(out.pair_count.sum().item()) == pairs
+    kern = [a.elapsed_time(b) for a, b in evs]
+    kern_ms = float(np.mean(kern))
+    flop_launch = (FLOP_REG * n_reg + FLOP_SING * n_sing) / n_launch
+    achieved = flop_launch / (kern_ms * 1e-3) / 1e12
+    status = out.status.cpu().numpy()
+    rec = {"workload": STRESS_DESC, "K": wl.K, "H": wl.H, "n_bound": wl.params["n_bound"],
+           "precision": "fp32c", "steps": 1, "warmup": "one 256-rollout launch",
+           "seconds_per_mppi_step": wall, "pair_interactions_per_s": pairs / wall,
+           "rollouts_per_s": wl.K / wall, "pairs_per_step": pairs, "launches": n_launch,
+           "rollout_kernel_ms_per_launch": kern_ms,
+           "rollout_kernel_ms_min_max": [float(min(kern)), float(max(kern))],
+           "kernel_timing": "HIP events around each 1024-rollout launch on its stream",
+           "nonfinite_rollouts": int(np.sum(status != 0)), "tuning": tuning,
+           "gpu_clock_after_timed_region": gpu_clock(),
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                        "traffic": measured_traffic("stress")}}
+    del db, out
+    ctx.close()
+    if with_oracle:
+        base, sub, o = cpu_baseline("stress", wl)
+        rec["cpu_baseline"] = base
+        ctx = V.Context(0)
+        rec["error_vs_oracle"] = {
+            name: stress_errors(V, ctx, sub, o, prec)
+            for name, prec in (("fp32c", V.FP32C), ("fp64", V.FP64))}
+        ctx.close()
+    return rec
+
+
+STRESS_ORACLE_STEPS = 4
+
+
+def stress_errors(V, ctx, sub, o, prec):
+    """GPU against the oracle on the stress subsample: the C4 error figures,
+    with the circulation drift max over steps of |sum Gamma_W (GPU) - sum
+    Gamma_W (oracle)|, where the wake's total after each solve is minus the
+    surface total (Kelvin row of the solve)."""
+    import torch
+    db = V.DeviceBatch(sub)
+    out = V.DeviceOutputs(db, final_wake=True, vel_last=True, gamma_s=True, traj=True)
+    ctx.rollout(sub.params, db, out, prec)
+    w, _, am, _ = ctx.mppi(out.cost, sub.lam, db.u_mean, db.u_eps)
+    torch.cuda.synchronize()
+    g = out.to_numpy()
+    vel = max(_rel_l2(g["vel_last"][g["out_off"][k]:g["out_off"][k] + g["n_vel_last"][k]],
+                      o["vel_last"][o["out_off"][k]:o["out_off"][k] + o["n_vel_last"][k]])
+              for k in range(sub.K))
+    seg_g, seg_o = [], []
+    for k in range(sub.K):
+        n = int(g["n_final"][k])
+        a0, b0 = int(g["out_off"][k]), int(o["out_off"][k])
+        seg_g.append(np.concatenate([g["wx"][a0:a0 + n], g["wz"][a0:a0 + n]]))
+        seg_o.append(np.concatenate([o["wx"][b0:b0 + n], o["wz"][b0:b0 + n]]))
+    drift = np.abs(g["gamma_s"].sum(axis=2) - o["gamma_s"].sum(axis=2))
+    return {"horizon": "%d steps, 64 rollouts (evenly spaced)" % sub.H,
+            "velocities_last_step_rel_l2_max": vel,
+            "gamma_s_rel_l2": _rel_l2(g["gamma_s"], o["gamma_s"]),
+            "traj_rel_l2": _rel_l2(g["traj"], o["traj"]),
+            "final_state_rel_l2": _rel_l2(g["g_final"], o["g_final"]),
+            "final_wake_positions_rel_l2": _rel_l2(np.concatenate(seg_g), np.concatenate(seg_o)),
+            "circulation_drift_max": float(drift.max()),
+            "wake_counts_equal": bool(np.array_equal(g["n_final"], o["n_final"])),
+            "mppi_weights_max_abs": float(np.max(np.abs(w.cpu().numpy() - o["mppi"]["w"]))),
+            "mppi_argmin_equal": int(am.item()) == o["mppi"]["argmin"]}
 
 
 def policy_bytes(K, H):
@@ -751,6 +893,9 @@ def main():
     from paper_2509_16079_amd import vpm as V
 
     wl, desc, prec_name, (steps_d, warm_d) = make_workload(args.workload)
+    if args.max_k is not None and args.max_k < wl.K:
+        wl = wl.subset(np.arange(args.max_k))
+        desc += "; first %d rollouts only" % args.max_k
     steps = steps_d if args.steps is None else args.steps
     warmup = warm_d if args.warmup is None else args.warmup
     prec_name = args.precision or prec_name
@@ -863,9 +1008,13 @@ def main():
     ctx.close()
     n_serve = args.serving_requests
     if n_serve is None:
-        n_serve = 16 if args.workload == "realtime" else 0
+        n_serve = 64 if args.workload == "realtime" and args.max_k is None else 0
     if n_serve > 0:
-        line["serving"] = serving(n_serve, sweep=args.serving_sweep)
+        line["serving"] = serving(n_serve, sweep=args.serving_sweep, slots=args.serving_slots,
+                                  tuning=args.tuning)
+    if args.stress_record == "on" or (args.stress_record is None and
+                                      args.workload == "realtime" and args.max_k is None):
+        line["stress"] = stress_record(args, with_oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         base, sub, o = cpu_baseline(args.workload, wl)
         line["cpu_baseline"] = base

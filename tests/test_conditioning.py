@@ -8,7 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2509_16079_amd import workloads as W
-from tests.golden.conditioning import divergence_curve
+from tests.golden.conditioning import divergence_curve, read_stress
 from tests.parity import rel_l2, run_oracle
 
 # (case, horizon, bar) -- the same horizons test_gpu_parity uses
@@ -53,3 +53,18 @@ def test_full_horizons_are_not():
     # the full realtime horizon amplifies FP64 rounding beyond 1e-6 on its own
     d = divergence_curve(W.realtime(K=2, H=120))
     assert d[-1] > 1e-7
+
+
+# The stress field (16376 vortices) is too slow for the CPU suite: its curves
+# come from tests/golden/conditioning_stress.txt, written by the committed
+# script from the oracle alone. The GPU stress horizon tests use H = 20.
+STRESS_H = 20
+
+
+def test_stress_horizon_is_well_conditioned():
+    g = read_stress()
+    i = STRESS_H // g["step"]
+    assert g["D"][i] <= 0.1 * 1e-10, g["D"][i]          # FP64 bar
+    assert g["S"][i] <= 0.3 * 1e-4, g["S"][i]           # FP32 bar
+    # and the full 150-step horizon is not: rounding alone grows past both bars
+    assert g["D"][-1] > 1e-10 and g["S"][-1] > 1e-4
