@@ -234,6 +234,30 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
                               const vpm_batch_in *in, vpm_batch_out *out,
                               void *stream);
 
+/* vpm_rollout_batch for callers that cannot allocate device memory in their
+ * hot loop (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results, with the kernels' scratch
+ * (the uneven-batch plan and the streaming workspace) taken from a static
+ * device array of the library of VPM_NOALLOC_SCRATCH_BYTES per GPU (mapped
+ * when the library's code is loaded on the GPU, held until the process ends)
+ * instead of context buffers. It calls no hipMalloc, hipFree or other
+ * allocating routine and creates no stream or event: the class kernels of an
+ * uneven batch run one after another on `stream`, and streamed rollouts run
+ * on as many workgroups (at most one per CU) as whole slots of
+ * (max_wake0 + 2H) x 24 B (FP32) or x 48 B (FP64) fit beside the plan
+ * (K x 4 B + 64 B, rounded up to 256 B). The plate inverse of params'
+ * geometry must already be cached in the context (vpm_reserve or an earlier
+ * vpm_rollout_batch with these params). Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents (the kernels initialise
+ * what they read): calls that overlap on one GPU, from any context or
+ * stream, race and must be ordered by the caller. Errors: those of
+ * vpm_rollout_batch, VPM_EINVAL if the plate inverse is not cached, and
+ * VPM_ECAPACITY if the plan or one streaming slot exceeds the array. */
+#define VPM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+VPM_API int vpm_rollout_batch_noalloc(vpm_ctx *ctx, const vpm_params *params,
+                                      const vpm_batch_in *in, vpm_batch_out *out,
+                                      void *stream);
+
 /* Prepare the context for later vpm_rollout_batch calls with these or smaller
  * sizes (K rollouts, H steps, initial wakes of at most max_wake0 vortices in
  * n_fields fields, the kernel variant set by vpm_set_path): builds the plate

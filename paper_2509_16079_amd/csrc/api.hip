@@ -41,6 +41,18 @@ int plate_inverse_device(vpm_ctx *ctx, const vpm_params *p, int mode,
   return VPM_OK;
 }
 
+// The cached inverse only (calls that must not allocate).
+int plate_inverse_cached(vpm_ctx *ctx, const vpm_params *p, int mode, const double **out) {
+  PlateKey key{p->n_bound, mode, p->chord, p->shed_frac, p->r_core};
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  auto it = ctx->plate_cache.find(key);
+  if (it == ctx->plate_cache.end())
+    return fail(VPM_EINVAL, "the plate inverse of this geometry is not built: call vpm_reserve "
+                            "(or vpm_rollout_batch) with these params first");
+  *out = it->second;
+  return VPM_OK;
+}
+
 bool stream_capturing(hipStream_t stream) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
@@ -83,6 +95,11 @@ VPM_API int vpm_create(vpm_ctx **out, int device) {
   if (!ok) {
     vpm_destroy(c);
     return fail(VPM_EDEVICE, "stream or event creation failed");
+  }
+  const int rc = vpm::static_scratch_address(device, &c->scratch);
+  if (rc != VPM_OK) {
+    vpm_destroy(c);
+    return rc;
   }
   *out = c;
   return VPM_OK;
@@ -128,7 +145,23 @@ VPM_API int vpm_rollout_batch(vpm_ctx *ctx, const vpm_params *params,
     rc = vpm::plate_inverse_device(ctx, params, VPM_SHED_TE, &kinv_te, capturing);
   if (rc != VPM_OK) return rc;
   return vpm::launch_rollout(ctx, params, in, out, kinv, kinv_te,
-                             static_cast<hipStream_t>(stream));
+                             static_cast<hipStream_t>(stream), false);
+}
+
+VPM_API int vpm_rollout_batch_noalloc(vpm_ctx *ctx, const vpm_params *params,
+                                      const vpm_batch_in *in, vpm_batch_out *out,
+                                      void *stream) {
+  if (!ctx) return fail(VPM_EINVAL, "ctx is NULL");
+  int rc = vpm_validate_batch(params, in, out);
+  if (rc != VPM_OK) return rc;
+  VPM_HIP_TRY(hipSetDevice(ctx->device));
+  const double *kinv = nullptr, *kinv_te = nullptr;
+  rc = vpm::plate_inverse_cached(ctx, params, params->shed_mode, &kinv);
+  if (rc == VPM_OK && params->gate)
+    rc = vpm::plate_inverse_cached(ctx, params, VPM_SHED_TE, &kinv_te);
+  if (rc != VPM_OK) return rc;
+  return vpm::launch_rollout(ctx, params, in, out, kinv, kinv_te,
+                             static_cast<hipStream_t>(stream), true);
 }
 
 VPM_API int vpm_set_tuning(vpm_ctx *ctx, int32_t kernel_class, int32_t targets_per_thread,

@@ -1332,7 +1332,7 @@ int launch_lds(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
 
 template <typename R, int TMAX, int NW, int TILE>
 int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
-                  hipStream_t stream, bool capturing) {
+                  hipStream_t stream, bool capturing, void *fixed_ws) {
   const int lds = stream_layout<R>(a.nb, a);
   if (lds + static_cast<int>(sizeof(Shared<R>)) > ctx->max_lds)
     return fail(VPM_ECAPACITY, "streaming kernel LDS exceeds the device limit");
@@ -1340,12 +1340,15 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
                                  : rollout_stream_kernel<R, TMAX, NW, TILE, false>;
   int rc = set_lds(kern, lds);
   if (rc != VPM_OK) return rc;
-  const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
-  rc = ensure_buffer(&ctx->ws, &ctx->ws_bytes, slot * grid, "streaming workspace", capturing);
-  if (rc != VPM_OK) return rc;
-  a.ws_src = ctx->ws;
-  a.ws_vel = static_cast<char *>(ctx->ws) +
-             (size_t)grid * a.cap * sizeof(typename SrcOf<R>::type);
+  void *ws = fixed_ws;  // the caller sized it for `grid` slots
+  if (!ws) {
+    const size_t slot = (size_t)a.cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
+    rc = ensure_buffer(&ctx->ws, &ctx->ws_bytes, slot * grid, "streaming workspace", capturing);
+    if (rc != VPM_OK) return rc;
+    ws = ctx->ws;
+  }
+  a.ws_src = ws;
+  a.ws_vel = static_cast<char *>(ws) + (size_t)grid * a.cap * sizeof(typename SrcOf<R>::type);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, stream, a, qu);
   VPM_HIP_TRY(hipGetLastError());
   return VPM_OK;
@@ -1384,20 +1387,20 @@ int launch_lds_tuned(vpm_ctx *ctx, KArgs a, int cap, int grid, const Queue &qu,
 
 template <typename R, int NW>
 int launch_stream_tuned(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu, hipStream_t stream,
-                        bool capturing, Tune t) {
+                        bool capturing, Tune t, void *fixed_ws = nullptr) {
   if constexpr (sizeof(R) == 8) {
-    return launch_stream<R, 2, NW, 64>(ctx, a, grid, qu, stream, capturing);
+    return launch_stream<R, 2, NW, 64>(ctx, a, grid, qu, stream, capturing, fixed_ws);
   } else {
     switch (t.tmax * 1000 + t.tile) {
-      case 1064: return launch_stream<R, 1, NW, 64>(ctx, a, grid, qu, stream, capturing);
-      case 1128: return launch_stream<R, 1, NW, 128>(ctx, a, grid, qu, stream, capturing);
-      case 1256: return launch_stream<R, 1, NW, 256>(ctx, a, grid, qu, stream, capturing);
-      case 2064: return launch_stream<R, 2, NW, 64>(ctx, a, grid, qu, stream, capturing);
-      case 2128: return launch_stream<R, 2, NW, 128>(ctx, a, grid, qu, stream, capturing);
-      case 2256: return launch_stream<R, 2, NW, 256>(ctx, a, grid, qu, stream, capturing);
-      case 4064: return launch_stream<R, 4, NW, 64>(ctx, a, grid, qu, stream, capturing);
-      case 4128: return launch_stream<R, 4, NW, 128>(ctx, a, grid, qu, stream, capturing);
-      case 4256: return launch_stream<R, 4, NW, 256>(ctx, a, grid, qu, stream, capturing);
+      case 1064: return launch_stream<R, 1, NW, 64>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 1128: return launch_stream<R, 1, NW, 128>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 1256: return launch_stream<R, 1, NW, 256>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 2064: return launch_stream<R, 2, NW, 64>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 2128: return launch_stream<R, 2, NW, 128>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 2256: return launch_stream<R, 2, NW, 256>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 4064: return launch_stream<R, 4, NW, 64>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 4128: return launch_stream<R, 4, NW, 128>(ctx, a, grid, qu, stream, capturing, fixed_ws);
+      case 4256: return launch_stream<R, 4, NW, 256>(ctx, a, grid, qu, stream, capturing, fixed_ws);
       default: return fail(VPM_EINVAL, "unsupported kernel tuning");
     }
   }
@@ -1407,6 +1410,90 @@ int launch_stream_tuned(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu, hipStr
 template <typename R> Tune class_tune(const vpm_ctx *ctx, int cls) {
   if constexpr (sizeof(R) == 8) return Tune{2, 64};
   return ctx->tune[cls];
+}
+
+// Bytes of one streaming-workspace slot (one resident workgroup's wake and
+// velocities) for wakes of capacity `cap`.
+template <typename R>
+size_t stream_slot_bytes(int cap) {
+  return (size_t)cap * (sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>));
+}
+
+// One batch of vpm_rollout_batch_noalloc: the kernels of run_batch with their
+// scratch (the uneven-batch plan, then the streaming workspace) in the
+// library's static device array [scratch, scratch + bytes), the streamed
+// class on as many workgroups as whole slots fit there (at most one per CU),
+// and the class kernels of an uneven batch one after another on the caller's
+// stream. Allocates nothing and creates no stream or event.
+template <typename R, int MINW_S, int NW_X>
+int run_batch_noalloc(vpm_ctx *ctx, KArgs a, int path, hipStream_t stream, char *scratch,
+                      size_t bytes) {
+  constexpr int kNwSmall = 4, kNwLarge = sizeof(R) == 4 ? 16 : 8;
+  std::lock_guard<std::mutex> lock(ctx->ws_mu);  // the tuning table
+  const int cap = a.cap;
+  const Tune t_s = class_tune<R>(ctx, VPM_CLASS_SMALL), t_l = class_tune<R>(ctx, VPM_CLASS_LARGE);
+  const Tune t_x = class_tune<R>(ctx, VPM_CLASS_STREAM);
+  const int cap_small = lds_capacity<R, kNwSmall>(a.nb, a.n_inv, t_s.tmax, ctx->max_lds / 4);
+  const int cap_large = lds_capacity<R, kNwLarge>(a.nb, a.n_inv, t_l.tmax, ctx->max_lds);
+  const Queue none{nullptr, nullptr, nullptr, 0};
+  const bool stream_only = path == VPM_PATH_STREAM;
+  const size_t slot = stream_slot_bytes<R>(cap);
+  auto stream_grid = [&](size_t room) {
+    size_t g = room / slot;
+    g = g < (size_t)ctx->n_cu ? g : (size_t)ctx->n_cu;
+    return (int)(g < (size_t)a.K ? g : (size_t)a.K);
+  };
+  if (a.n_fields == 1 || path == VPM_PATH_LDS || stream_only) {
+    if (!stream_only && cap <= cap_small)
+      return launch_lds_tuned<R, MINW_S, kNwSmall>(ctx, a, cap, a.K, none, stream, t_s);
+    if (!stream_only && cap <= cap_large)
+      return launch_lds_tuned<R, 1, kNwLarge>(ctx, a, cap, a.K, none, stream, t_l);
+    if (path == VPM_PATH_LDS)
+      return fail(VPM_ECAPACITY, "wake capacity " + std::to_string(cap) +
+                                     " does not fit the LDS-resident kernel");
+    const int grid = stream_grid(bytes);
+    if (grid < 1)
+      return fail(VPM_ECAPACITY, "one streaming slot of wake capacity " + std::to_string(cap) +
+                                     " exceeds the static scratch of " +
+                                     std::to_string(bytes) + " bytes");
+    return launch_stream_tuned<R, NW_X>(ctx, a, grid, none, stream, false, t_x, scratch);
+  }
+  // uneven batch: the plan at the start of the scratch, 256-byte aligned
+  const size_t plan_bytes = ((size_t)a.K * sizeof(int32_t) + 64 + 255) & ~size_t(255);
+  if (plan_bytes > bytes)
+    return fail(VPM_ECAPACITY, "the plan of " + std::to_string(a.K) +
+                                   " rollouts exceeds the static scratch");
+  int2 *range = reinterpret_cast<int2 *>(scratch);
+  int32_t *next = reinterpret_cast<int32_t *>(scratch + 32);
+  int32_t *list = reinterpret_cast<int32_t *>(scratch + 64);
+  int grid_x = 0;
+  if (cap > cap_large) {
+    grid_x = stream_grid(bytes - plan_bytes);
+    if (grid_x < 1)
+      return fail(VPM_ECAPACITY, "one streaming slot of wake capacity " + std::to_string(cap) +
+                                     " does not fit the static scratch beside the plan");
+  }
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, a.K, a.H,
+                     a.max_wake0, a.n_fields, a.field_off, a.field_of, cap_small,
+                     cap_large, list, range, next);
+  VPM_HIP_TRY(hipGetLastError());
+  int rc = VPM_OK;
+  if (cap > cap_large) {
+    rc = launch_stream_tuned<R, NW_X>(ctx, a, grid_x, Queue{list, next, range, 0}, stream, false,
+                                      t_x, scratch + plan_bytes);
+    if (rc != VPM_OK) return rc;
+  }
+  if (cap > cap_small) {
+    const int c1 = cap < cap_large ? cap : cap_large;
+    const int grid = a.K < ctx->n_cu ? a.K : ctx->n_cu;
+    rc = launch_lds_tuned<R, 1, kNwLarge>(ctx, a, c1, grid, Queue{list, next, range, 1}, stream,
+                                          t_l);
+    if (rc != VPM_OK) return rc;
+  }
+  const int c2 = cap < cap_small ? cap : cap_small;
+  const int grid = a.K < 4 * ctx->n_cu ? a.K : 4 * ctx->n_cu;
+  return launch_lds_tuned<R, MINW_S, kNwSmall>(ctx, a, c2, grid, Queue{list, next, range, 2},
+                                               stream, t_s);
 }
 
 // One batch in a given precision. Uniform batches (one field) run one
@@ -1592,7 +1679,7 @@ int lds_resident_capacity(int nb, int precision) {
 
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
                    vpm_batch_out *out, const double *kinv_t, const double *kinv_te,
-                   hipStream_t stream) {
+                   hipStream_t stream, bool noalloc) {
   KArgs a{};
   a.K = in->K;
   a.H = in->H;
@@ -1659,9 +1746,48 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.gb_final = out->gb_final;
   a.fb_gain = in->fb_gain;
   a.fb_xref = in->fb_gain ? in->fb_xref : nullptr;
+  if (noalloc) {
+    char *sc = static_cast<char *>(ctx->scratch);
+    if (!sc) return fail(VPM_EDEVICE, "the library's static scratch is not mapped");
+    if (p->precision == VPM_FP64)
+      return run_batch_noalloc<double, 2, 8>(ctx, a, ctx->path, stream, sc, kScratchBytes);
+    return run_batch_noalloc<float, 4, 16>(ctx, a, ctx->path, stream, sc, kScratchBytes);
+  }
   if (p->precision == VPM_FP64)
     return run_batch<double, 2, 8>(ctx, a, ctx->path, stream);
   return run_batch<float, 4, 16>(ctx, a, ctx->path, stream);
+}
+
+// The scratch of vpm_rollout_batch_noalloc: device memory of the library
+// itself, one copy per GPU the library runs on, held until the process ends.
+// In host code `scratch` names a host-side stand-in; the device address of
+// each GPU's copy comes from hipGetSymbolAddress (static_scratch_address).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch_address(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices)
+    return fail(VPM_EDEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    int cur = -1;
+    VPM_HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) return fail(VPM_EDEVICE, "the device must be current");
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(VPM_EDEVICE, std::string("hipGetSymbolAddress of the static scratch: ") +
+                                   hipGetErrorString(e));
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return VPM_OK;
 }
 
 }  // namespace vpm

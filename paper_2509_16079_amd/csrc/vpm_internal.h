@@ -69,6 +69,7 @@ struct vpm_ctx {
   size_t replan_bytes = 0;
   void *fd = nullptr;
   size_t fd_bytes = 0;
+  void *scratch = nullptr;  // this device's static scratch (noalloc calls)
 };
 
 namespace vpm {
@@ -98,9 +99,18 @@ int reserve_rollout(vpm_ctx *ctx, const vpm_params *p, int K, int H, int max_wak
 
 // kinv_t: inverse of the plate system of p->shed_mode; kinv_te: of the
 // trailing-edge-only system when the separation gate is on (else NULL).
+// noalloc: the scratch comes from the library's static device array
+// (vpm_rollout_batch_noalloc) instead of the context's buffers.
 int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
                    vpm_batch_out *out, const double *kinv_t, const double *kinv_te,
-                   hipStream_t stream);
+                   hipStream_t stream, bool noalloc);
+
+// Size of the static scratch of vpm_rollout_batch_noalloc.
+constexpr size_t kScratchBytes = VPM_NOALLOC_SCRATCH_BYTES;
+
+// Device address of this device's copy of the static scratch (looked up once
+// per device, which must be current).
+int static_scratch_address(int device, void **out);
 int launch_plate_solve(const vpm_params *p, int B, const double *pose,
                        const double *vw_c, const double *sum_gw, int mode,
                        const double *kinv_t, double *gamma_s,

@@ -69,6 +69,8 @@ def lib():
         L.vpm_validate_batch.argtypes = [C.POINTER(Params), C.POINTER(BatchIn), C.POINTER(BatchOut)]
         L.vpm_rollout_batch.argtypes = [_P, C.POINTER(Params), C.POINTER(BatchIn),
                                         C.POINTER(BatchOut), _P]
+        L.vpm_rollout_batch_noalloc.argtypes = [_P, C.POINTER(Params), C.POINTER(BatchIn),
+                                                C.POINTER(BatchOut), _P]
         L.vpm_plate_solve.argtypes = [_P, C.POINTER(Params), _I, _P, _P, _P, _I, _P, _P]
         L.mppi_weights.argtypes = [_P, _I, _I, _P, _D, _P, _P, _P, _P, _P, _P, _P]
         L.vpm_set_path.argtypes = [_P, C.c_int]
@@ -322,16 +324,18 @@ class Context:
                                 int(n_fields)), "vpm_reserve")
 
     def rollout(self, params: dict, db: DeviceBatch, out: DeviceOutputs, precision=FP32C,
-                stream=None, k0=0, k1=None):
-        """Enqueue ``vpm_rollout_batch`` on ``stream`` (default: torch's current)
-        for rollouts [k0, k1) of the batch (default: all)."""
+                stream=None, k0=0, k1=None, noalloc=False):
+        """Enqueue ``vpm_rollout_batch`` (``vpm_rollout_batch_noalloc`` with
+        ``noalloc``) on ``stream`` (default: torch's current) for rollouts
+        [k0, k1) of the batch (default: all)."""
         p = make_params(params, precision)
         if k0 == 0 and k1 is None:
             bi, bo = db.batch_in(), out.batch_out()
         else:
             bi, bo = db.batch_in(k0, k1), out.batch_out(k0, k1)
-        check(lib().vpm_rollout_batch(self.h, C.byref(p), C.byref(bi), C.byref(bo),
-                                      _stream_handle(stream)), "vpm_rollout_batch")
+        fn = lib().vpm_rollout_batch_noalloc if noalloc else lib().vpm_rollout_batch
+        check(fn(self.h, C.byref(p), C.byref(bi), C.byref(bo), _stream_handle(stream)),
+              "vpm_rollout_batch_noalloc" if noalloc else "vpm_rollout_batch")
         return out
 
     def plate_solve(self, params: dict, pose, vw_c, sum_gw, shed_mode=SHED_BOTH, stream=None):
