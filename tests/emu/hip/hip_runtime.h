@@ -75,6 +75,12 @@ inline hipError_t hipMemcpy(void *d, const void *s, size_t n, int) { memcpy(d, s
 inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, int, hipStream_t) { memcpy(d, s, n); return hipSuccess; }
 inline hipError_t hipSetDevice(int) { return hipSuccess; }
 inline hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
+inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+// the emulated device is the host: a device variable's address is its own
+template <class T> inline hipError_t hipGetSymbolAddress(void **p, T *sym) {
+  *p = static_cast<void *>(sym);
+  return hipSuccess;
+}
 inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) {
   memset(p, 0, sizeof(*p));
   strcpy(p->gcnArchName, "gfx950:sramecc+:xnack-");
