@@ -78,6 +78,8 @@ template <> struct PassAOf<double> { using type = Src64; };
 template <typename R, int NW> constexpr bool lds_scaled() { return sizeof(R) == 4 && NW == 4; }
 
 template <typename R> struct alignas(2 * sizeof(R)) Vec2 { R x, z; };
+// A bound vortex as pass B reads it: position and strength / (2 pi).
+template <typename R> struct alignas(4 * sizeof(R)) Bound { R x, z, g, pad; };
 
 // Kernel argument block, filled on the host.
 struct KArgs {
@@ -109,8 +111,9 @@ template <typename R> struct Shared {
   R g[7], gn[7];
   R le[2], et[2], en[2], xw[2], xwd[2], lev[2], tev[2];
   R ct, st;  // cos and sin of the pitch at the start of the step
-  R bpos[kMaxBound][2];
-  R bgam[kMaxBound];
+  // bound vortices of the step; entries N_b .. (N_b rounded up to 8) - 1
+  // are zero, so pass B reads whole blocks of 8 without clamping
+  Bound<R> bnd[kMaxBound];
   R shed_g[2];
   double gb_prev[kMaxBound];
   double bvec[kMaxBound + 2];
@@ -288,6 +291,15 @@ __device__ inline void accumulate(const S *__restrict__ src,
     }
     fold_tile<R, T>(sx, sz, cx, cz, ax, az);
   }
+}
+
+// The thread index, opaque to the compiler at this point: addresses that
+// setup and finish derive from it are then computed per rollout instead of
+// being hoisted out of the persistent rollout loop, where these per-lane
+// 64-bit values would stay live across every step and spill.
+__device__ inline int opaque_tid(int tid) {
+  asm volatile("" : "+v"(tid));
+  return tid;
 }
 
 // All lanes of a wave: its LDS writes are visible to its own later reads.
@@ -603,9 +615,9 @@ __device__ __forceinline__ void solve_section(
   const double sarm = a.rho * wave_sum(tm);
   if (on) {
     sh.gb_prev[lane] = gbj;
-    sh.bpos[lane][0] = R(bx);
-    sh.bpos[lane][1] = R(bz);
-    sh.bgam[lane] = R(gbj * kInv2Pi);
+    sh.bnd[lane] = Bound<R>{R(bx), R(bz), R(gbj * kInv2Pi), R(0)};
+  } else if (lane < ((nb + 7) & ~7)) {
+    sh.bnd[lane] = Bound<R>{R(0), R(0), R(0), R(0)};
   }
   if (lane == 0) {
     const double fwx = lb * a.span * sdp * enx, fwz = lb * a.span * sdp * enz;
@@ -666,14 +678,26 @@ __device__ inline void pass_b_sum(const KArgs &a, const Shared<R> &sh, R x, R z,
   if (q0 <= 0 && q1 > 0) reg_term(x - sh.lev[0], z - sh.lev[1], sh.shed_g[0], rc4, ex, ez);
   if (q0 <= 1 && q1 > 1) reg_term(x - sh.tev[0], z - sh.tev[1], sh.shed_g[1], rc4, ex, ez);
   const int jlo = q0 > 2 ? q0 - 2 : 0, jhi = q1 - 2;
+  if (jlo == 0 && jhi == a.nb) {
+    // all bound vortices: whole blocks of 8 (zero-strength padding adds
+    // exactly nothing), constant LDS offsets, no per-entry selects
+    for (int j0 = 0; j0 < jhi; j0 += 8) {
+      Bound<R> b[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) b[q] = sh.bnd[j0 + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sing_term(x - b[q].x, z - b[q].z, b[q].g, ex, ez);
+    }
+    return;
+  }
   for (int j0 = jlo; j0 < jhi; j0 += 8) {
     R bx[8], bz[8], bg[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int j = j0 + q < jhi ? j0 + q : jhi - 1;
-      bx[q] = sh.bpos[j][0];
-      bz[q] = sh.bpos[j][1];
-      bg[q] = j0 + q < jhi ? sh.bgam[j] : R(0);
+      bx[q] = sh.bnd[j].x;
+      bz[q] = sh.bnd[j].z;
+      bg[q] = j0 + q < jhi ? sh.bnd[j].g : R(0);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) sing_term(x - bx[q], z - bz[q], bg[q], ex, ez);
@@ -991,7 +1015,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
     const int k = claim(qu, sh, tid, fallback);
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, scl, k, tid, kThr)) continue;
+    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr)) continue;
     __syncthreads();
 
     for (int n = 0; n < a.H; ++n) {
@@ -1067,7 +1091,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
       __syncthreads();
     }
-    finish(a, sh, src, k, tid, kThr);
+    finish(a, sh, src, k, opaque_tid(tid), kThr);
   }
 }
 
@@ -1144,7 +1168,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     }
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, scl, k, tid, kThr)) continue;
+    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr)) continue;
     __syncthreads();
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
@@ -1181,7 +1205,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
       if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
       __syncthreads();
     }
-    finish(a, sh, src, k, tid, kThr);
+    finish(a, sh, src, k, opaque_tid(tid), kThr);
   }
 }
 
