@@ -272,12 +272,14 @@ __device__ inline void fold_tile(R (&sx)[T], R (&sz)[T], R (&cx)[T], R (&cz)[T],
 }
 
 // Sources [s_lo, s_hi) of `src` onto the T targets of this lane, folded
-// every TILE sources.
+// every TILE sources. `fresh` (uniform): the sums and their compensations are
+// still zero on entry, so the first tile is taken as it is — the fold of a
+// tile into zero is exact (TwoSum(0, a) = (a, 0)) and only costs issue slots.
 template <typename R, int T, int TILE, typename S>
 __device__ inline void accumulate(const S *__restrict__ src,
                                   int s_lo, int s_hi, const R (&tx)[T],
                                   const R (&tz)[T], R rc4, R (&sx)[T], R (&sz)[T],
-                                  R (&cx)[T], R (&cz)[T]) {
+                                  R (&cx)[T], R (&cz)[T], bool fresh) {
   for (int s0 = s_lo; s0 < s_hi; s0 += TILE) {
     const int s1 = min(s0 + TILE, s_hi);
     R ax[T], az[T];
@@ -289,7 +291,15 @@ __device__ inline void accumulate(const S *__restrict__ src,
 #pragma unroll
       for (int j = 0; j < T; ++j) pair_term(tx[j], tz[j], v, rc4, ax[j], az[j]);
     }
-    fold_tile<R, T>(sx, sz, cx, cz, ax, az);
+    if (fresh && s0 == s_lo) {
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        sx[j] = ax[j];
+        sz[j] = az[j];
+      }
+    } else {
+      fold_tile<R, T>(sx, sz, cx, cz, ax, az);
+    }
   }
 }
 
@@ -325,7 +335,7 @@ __device__ inline void accumulate_staged(const Src32 *__restrict__ src, Scl32 *s
     const int cnt = min(kStage, s_hi - b0);
     for (int q = lane; q < cnt; q += 64) stage[q] = pass_a_source(src[b0 + q], rc);
     wave_lds_sync();
-    accumulate<float, T, TILE>(stage, 0, cnt, tx, tz, 0.0f, sx, sz, cx, cz);
+    accumulate<float, T, TILE>(stage, 0, cnt, tx, tz, 0.0f, sx, sz, cx, cz, b0 == s_lo);
     wave_lds_sync();  // every lane done with the batch before it is overwritten
   }
 }
@@ -927,7 +937,7 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
     accumulate_staged<T, TILE>(pa, reinterpret_cast<Scl32 *>(red + wave * 64 * T), s_lo, s_hi,
                                rc, lane, tx, tz, sx, sz, cx, cz);
   else
-    accumulate<R, T, TILE>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz);
+    accumulate<R, T, TILE>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz, true);
   Vec2<R> *out = red + wave * 64 * T;
 #pragma unroll
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
@@ -949,7 +959,7 @@ __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
   if (q < g) {
     const int len = s_hi - s_lo;
     accumulate<R, 1, TILE>(pa, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
-                     sx, sz, cx, cz);
+                     sx, sz, cx, cz, true);
   }
   red[wave * 64 + lane] = Vec2<R>{sx[0] + cx[0], sz[0] + cz[0]};
 }
@@ -1056,10 +1066,12 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         const int span = 64 * T;
         const int parts = tail ? 64 / tail : 1;
         for (int t = tid; t < span && c0 + t < NT; t += kThr) {
-          double vx = 0.0, vz = 0.0;
+          // wave 0's first part starts the sum (adding it to zero is exact)
+          const Vec2<R> r0 = red[t];
+          double vx = double(r0.x), vz = double(r0.z);
 #pragma unroll
           for (int w = 0; w < NW; ++w) {
-            for (int q = 0; q < parts; ++q) {
+            for (int q = (w == 0 ? 1 : 0); q < parts; ++q) {
               const Vec2<R> r = red[w * span + q * tail + t];
               vx += double(r.x);
               vz += double(r.z);
@@ -1116,7 +1128,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
     const int cnt = min(kStreamTile, n_w - s0);
     for (int q = tid; q < cnt; q += 64 * NW) tile[q] = pass_a_source(src[head + s0 + q], rc);
     __syncthreads();
-    accumulate<R, T, TILE>(tile, 0, cnt, tx, tz, rc4, sx, sz, cx, cz);
+    accumulate<R, T, TILE>(tile, 0, cnt, tx, tz, rc4, sx, sz, cx, cz, s0 == 0);
     __syncthreads();
   }
 #pragma unroll

@@ -284,3 +284,28 @@ def test_table1_configuration_full_horizon(ctx, prec):
     hold over all 80 steps."""
     wl = W.table1(16)
     _horizon_parity(ctx, wl, prec)
+
+
+@pytest.mark.parametrize("prec,H", [(V.FP32C, 15), (V.FP64, 30)])
+def test_inputs_that_binary32_cannot_hold(ctx, prec, H):
+    """The generator rounds every value to binary32 so that both precisions
+    start from the same numbers; here the wake, the glider state, the
+    controls and the plate parameters carry FP64 digits beyond binary32 (a
+    relative offset of ~1e-9), so the FP32C path's own conversion of its
+    inputs is exercised: FP32C stays within its bar, FP64 within its own."""
+    from dataclasses import replace
+    wl = W.realtime(K=8, H=H)
+    rng = np.random.default_rng(77)
+    jig = lambda a: np.asarray(a, dtype=np.float64) * (1.0 + 1e-9 * rng.uniform(0.5, 1.5,
+                                                                                np.shape(a)))
+    p = dict(wl.params)
+    for key in ("chord", "r_core", "rho", "mass", "inertia", "l_wing", "l_elev"):
+        p[key] = float(jig(p[key]))
+    wl = replace(wl, params=p, wx=jig(wl.wx), wz=jig(wl.wz), wg=jig(wl.wg), g0=jig(wl.g0),
+                 u_eps=jig(wl.u_eps) + 1e-12, u_mean=wl.u_mean + 3e-11, name="unrounded")
+    assert not np.array_equal(wl.wx, wl.wx.astype(np.float32).astype(np.float64))
+    g = V.run_workload(ctx, wl, prec, traj=True, gamma_s=True)
+    o = run_oracle(wl, traj=True, gamma_s=True)
+    for key in ("traj", "gamma_s", "g_final"):
+        e = rel_l2(g[key], o[key])
+        assert e <= TOL[prec], describe("unrounded inputs " + key, err=e)
