@@ -312,6 +312,14 @@ __device__ inline int opaque_tid(int tid) {
   return tid;
 }
 
+// A 64-bit zero made where it is used: a shared zero register pair
+// hoisted out of the rollout loop would be live across every step and spill.
+__device__ inline long long opaque_zero64() {
+  long long z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
 // All lanes of a wave: its LDS writes are visible to its own later reads.
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -354,6 +362,20 @@ __device__ inline void surface_point(const Shared<R> &sh, int t, int nb, R lb,
     s = c + ds;  // TEV release point
   px = sh.le[0] + s * sh.et[0];
   pz = sh.le[1] + s * sh.et[1];
+}
+
+// Position of pass-A target t of the LDS kernels: the step's surface points
+// sit in the n_surf entries just below the wake (src[head - n_surf ..]), so
+// every target is one entry of src.
+template <typename R>
+__device__ inline void lds_target(const typename SrcOf<R>::type *src, int t, int NT,
+                                  int head, int n_surf, R &px, R &pz) {
+  px = pz = R(0);
+  if (t < NT) {
+    const auto v = src[head - n_surf + t];
+    px = v.x;
+    pz = v.z;
+  }
 }
 
 // Position of pass-A target t: surface points first, then the wake.
@@ -479,12 +501,12 @@ __device__ void prologue(const KArgs &a, Shared<R> &sh,
   }
 }
 
-// Load rollout k's initial state. Returns false (after writing the failure
-// outputs) when its field is invalid or larger than max_wake0; uniform over
-// the workgroup.
+// Load rollout k's initial state, the wake from entry `base` of src (and
+// scl) on. Returns false (after writing the failure outputs) when its field
+// is invalid or larger than max_wake0; uniform over the workgroup.
 template <typename R>
 __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *src,
-                      Scl32 *scl, int k, int tid, int nthr) {
+                      Scl32 *scl, int k, int tid, int nthr, int base) {
   using Src = typename SrcOf<R>::type;
   const int nb = a.nb;
   const int fo = a.field_of ? a.field_of[k] : k;
@@ -496,7 +518,7 @@ __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *sr
     if (tid == 0) {
       a.cost[k] = INFINITY;
       a.status[k] = n0 < 0 ? VPM_ROLLOUT_BADFIELD : VPM_ROLLOUT_CAPACITY;
-      if (a.pair_count) a.pair_count[k] = 0;
+      if (a.pair_count) a.pair_count[k] = opaque_zero64();
       if (a.n_final) a.n_final[k] = 0;
       if (a.n_vel_last) a.n_vel_last[k] = 0;
       if (a.gb_final)
@@ -505,8 +527,8 @@ __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *sr
     return false;
   }
   for (int q = tid; q < n0; q += nthr) {
-    src[q] = Src{R(a.wx[f0 + q]), R(a.wz[f0 + q]), R(a.wg[f0 + q] * kInv2Pi), R(0)};
-    rescale(scl, q, src[q], float(a.r_core));
+    src[base + q] = Src{R(a.wx[f0 + q]), R(a.wz[f0 + q]), R(a.wg[f0 + q] * kInv2Pi), R(0)};
+    rescale(scl, base + q, src[base + q], float(a.r_core));
   }
   if (tid < 7) {
     sh.g[tid] = R(a.g0[7 * k + tid]);
@@ -514,16 +536,21 @@ __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *sr
   }
   if (tid < nb) sh.gb_prev[tid] = a.gb0[(size_t)k * nb + tid];
   if (tid == 0) {
-    sh.head = 0;
+    sh.head = base;
     sh.n_w = n0;
     sh.status = 0;
-    sh.pairs = 0;
+    sh.pairs = opaque_zero64();
     for (int q = 0; q < kMaxPairs; ++q) {
       int pa = -1, pb = -1;
       if (q < a.n_pairs && a.pairs) {
         pa = a.pairs[(size_t)k * 2 * a.n_pairs + 2 * q];
         pb = a.pairs[(size_t)k * 2 * a.n_pairs + 2 * q + 1];
-        if (pa < 0 || pb < 0 || pa >= n0 || pb >= n0 || pa == pb) pa = pb = -1;
+        if (pa < 0 || pb < 0 || pa >= n0 || pb >= n0 || pa == pb) {
+          pa = pb = -1;
+        } else {
+          pa += base;
+          pb += base;
+        }
       }
       sh.pa[q] = pa;
       sh.pb[q] = pb;
@@ -930,7 +957,7 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
   R tx[T], tz[T], sx[T], sz[T], cx[T], cz[T];
 #pragma unroll
   for (int j = 0; j < T; ++j) {
-    target_pos(a, sh, src, c0 + lane + 64 * j, NT, head, tx[j], tz[j]);
+    lds_target(src, c0 + lane + 64 * j, NT, head, 2 * a.nb + 3, tx[j], tz[j]);
     sx[j] = sz[j] = cx[j] = cz[j] = R(0);
   }
   if constexpr (std::is_same_v<S, Src32>)
@@ -955,7 +982,7 @@ __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
   const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
   const int g = 64 / r, t = lane % r, q = lane / r;
   R tx[1], tz[1], sx[1] = {R(0)}, sz[1] = {R(0)}, cx[1] = {R(0)}, cz[1] = {R(0)};
-  target_pos(a, sh, src, c0 + t, NT, head, tx[0], tz[0]);
+  lds_target(src, c0 + t, NT, head, 2 * a.nb + 3, tx[0], tz[0]);
   if (q < g) {
     const int len = s_hi - s_lo;
     accumulate<R, 1, TILE>(pa, s_lo + (len * q) / g, s_lo + (len * (q + 1)) / g, tx, tz, rc4,
@@ -1025,7 +1052,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
     const int k = claim(qu, sh, tid, fallback);
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr)) continue;
+    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr, n_surf)) continue;
     __syncthreads();
 
     for (int n = 0; n < a.H; ++n) {
@@ -1036,6 +1063,16 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       rotate_priority(sh.slot, n);
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
       const int NT = n_surf + n_w;
+      // the step's surface points (collocation, bound, release) as pass-A
+      // targets in the n_surf entries below the wake, which hold no live
+      // vortex (the wake starts at n_surf and only moves up as it merges)
+      if (tid < n_surf) {
+        R px, pz;
+        surface_point(sh, tid, a.nb, R(a.chord / a.nb), R(a.shed_frac * a.chord), R(a.chord),
+                      px, pz);
+        src[head - n_surf + tid] = Src{px, pz, R(0), R(0)};
+      }
+      __syncthreads();
       // this step's control, loaded now so its latency hides behind pass A
       double u_m = 0.0, u_e = 0.0;
       if (tid == 0) {
@@ -1047,11 +1084,14 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       const int s_hi = head + (n_w * (wave + 1)) / NW;
       for (int c0 = 0; c0 < NT;) {
         const int rem = NT - c0;
-        // largest chunk at least 3/4 full (fewer chunks, barriers and
-        // cross-wave combines for a few idle target slots); a tail below 64
-        // takes T=1
-        int T = TMAX;
-        while (T > 1 && 48 * T > rem) T >>= 1;
+        // largest chunk of 4, 3, 2 or 1 targets per lane that is at least 3/4
+        // full (fewer chunks, barriers and cross-wave combines for a few idle
+        // target slots; the 3-target chunk keeps the last chunk of a step
+        // fuller than powers of two alone); a tail below 64 takes T=1
+        int T = 1;
+        if (TMAX >= 4 && 48 * 4 <= rem) T = 4;
+        else if (TMAX >= 4 && 48 * 3 <= rem) T = 3;
+        else if (TMAX >= 2 && 48 * 2 <= rem) T = 2;
         const int tail = rem < 32 ? rem : 0;  // tails of 32..63 keep a lane each
         if (tail) {
           lds_pass_a_tail<R, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
@@ -1059,6 +1099,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
           switch (T) {
             case 1: lds_pass_a_chunk<R, 1, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
             case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 3: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 3, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
             default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
           }
         }
@@ -1180,7 +1221,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     }
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr)) continue;
+    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr, 0)) continue;
     __syncthreads();
     for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
@@ -1304,13 +1345,16 @@ template <typename R, int NW> constexpr size_t lds_per_vortex() {
   return sizeof(typename SrcOf<R>::type) + sizeof(Vec2<R>) + scaled_bytes<R, NW>();
 }
 
+// The wake arrays (src, its scaled copy, vel) hold n_surf + cap entries: the
+// wake from entry n_surf on, the step's surface points just below it.
 template <typename R, int NW>
 int lds_layout(int cap, int nb, int tmax, KArgs &a) {
   constexpr int nw = NW;
+  const size_t ent = (size_t)cap + 2 * nb + 3;
   size_t off = 0;
-  off += (size_t)cap * sizeof(typename SrcOf<R>::type);
+  off += ent * sizeof(typename SrcOf<R>::type);
   a.off_scl = static_cast<int>(off);
-  off += (size_t)cap * scaled_bytes<R, NW>();
+  off += ent * scaled_bytes<R, NW>();
   off = (off + 15) & ~size_t(15);
   a.off_kinv = static_cast<int>(off);
   off += (size_t)a.n_inv * sizeof(double);
@@ -1320,7 +1364,7 @@ int lds_layout(int cap, int nb, int tmax, KArgs &a) {
   a.off_red = static_cast<int>(off);
   off += red_bytes<R>(nw, tmax);
   a.off_vel = static_cast<int>(off);
-  off += (size_t)cap * sizeof(Vec2<R>);
+  off += ent * sizeof(Vec2<R>);
   return static_cast<int>(off);
 }
 
@@ -1393,7 +1437,9 @@ int launch_stream(vpm_ctx *ctx, KArgs a, int grid, const Queue &qu,
 // Largest capacity a workgroup of the LDS kernel can hold within `bytes`.
 template <typename R, int NW>
 int lds_capacity(int nb, int n_inv, int tmax, size_t bytes) {
-  const size_t fixed = lds_fixed_bytes<R>(nb, n_inv, NW, tmax);
+  // the surface-point entries below the wake take n_surf vortex records
+  const size_t fixed = lds_fixed_bytes<R>(nb, n_inv, NW, tmax) +
+                       (size_t)(2 * nb + 3) * lds_per_vortex<R, NW>();
   return bytes > fixed ? static_cast<int>((bytes - fixed) / lds_per_vortex<R, NW>()) : 0;
 }
 
