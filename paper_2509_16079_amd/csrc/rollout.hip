@@ -320,6 +320,25 @@ __device__ inline long long opaque_zero64() {
   return z;
 }
 
+// +inf as a double made where it is used, for the same reason.
+__device__ inline double opaque_inf64() {
+  double v = INFINITY;
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// The kernel's arguments (the first kernel argument, at offset 0 of the
+// kernarg segment), re-read where this is called: through an address the
+// compiler cannot see through, argument loads are not hoisted across the
+// rollout and step loops, where the many argument registers would stay live
+// and spill to VGPR lanes (every read back costs a VALU issue slot).
+__device__ inline const KArgs &fresh_args(const KArgs &) {
+  using CK = __attribute__((address_space(4))) const KArgs;
+  CK *p = (CK *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const KArgs *)p;
+}
+
 // All lanes of a wave: its LDS writes are visible to its own later reads.
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -465,7 +484,7 @@ __device__ __noinline__ double wing_aoa(double th, double xd, double zd, double 
 // out-of-line call alone changes its register allocation), which costs the
 // plain open-loop instances a few per cent.
 template <typename R, bool EXT>
-__device__ void prologue(const KArgs &a, Shared<R> &sh,
+__device__ __forceinline__ void prologue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src, Scl32 *scl, int n) {
   geometry(a, sh);
   int mode = a.mode;
@@ -516,7 +535,7 @@ __device__ bool setup(const KArgs &a, Shared<R> &sh, typename SrcOf<R>::type *sr
   if (n0 < 0 || n0 > a.max_wake0) {
     if (tid < 7) a.g_final[7 * k + tid] = a.g0[7 * k + tid];
     if (tid == 0) {
-      a.cost[k] = INFINITY;
+      a.cost[k] = opaque_inf64();
       a.status[k] = n0 < 0 ? VPM_ROLLOUT_BADFIELD : VPM_ROLLOUT_CAPACITY;
       if (a.pair_count) a.pair_count[k] = opaque_zero64();
       if (a.n_final) a.n_final[k] = 0;
@@ -856,7 +875,7 @@ __device__ __forceinline__ void pass_b(const KArgs &a, const Shared<R> &sh,
 // Thread 0 at the end of a step: merging and the glider step; then, unless
 // it is the last step, the next step's prologue.
 template <typename R, bool EXT>
-__device__ void epilogue(const KArgs &a, Shared<R> &sh,
+__device__ __forceinline__ void epilogue(const KArgs &a, Shared<R> &sh,
                          typename SrcOf<R>::type *src, Scl32 *scl, int k, int n, int n_w) {
   using Src = typename SrcOf<R>::type;
   const int nb = a.nb, m = n_w + sh.n_shed;
@@ -898,7 +917,7 @@ __device__ void finish(const KArgs &a, const Shared<R> &sh,
       const double d = gi - a.x_goal[i];
       j += a.q_diag[i] * d * d;
     }
-    a.cost[k] = finite ? j : INFINITY;
+    a.cost[k] = finite ? j : opaque_inf64();
     a.status[k] = sh.status | (finite ? 0 : VPM_ROLLOUT_NONFINITE);
     if (a.pair_count) a.pair_count[k] = sh.pairs;
     if (a.n_final) a.n_final[k] = sh.n_w;
@@ -991,6 +1010,102 @@ __device__ void lds_pass_a_tail(const KArgs &a, const Shared<R> &sh,
   red[wave * 64 + lane] = Vec2<R>{sx[0] + cx[0], sz[0] + cz[0]};
 }
 
+// x / d for x < 2^24 and 1 <= d <= 256 as mulhi(x, ceil(2^32 / d)): the
+// multiplier exceeds 2^32 / d by e / d with e < d, so the product's excess
+// x e / 2^32 stays below 1 / d and cannot carry the quotient past an integer.
+__device__ inline uint32_t mulhi(uint32_t x, uint32_t m) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(x) * m) >> 32);
+}
+
+// Spread chunks of the FP32 small class. A step's last pass-A chunk holds
+// r < 64 TMAX targets; instead of 64 T target slots per wave against a
+// quarter of the sources each (up to 3/4 of the slots idle), every one of
+// the 256 lanes takes T targets against one of P equal source parts, with
+// G = ceil(r / T) target groups and P = floor(256 / G) parts. plan[ti][r]
+// holds, for TMAX = 1 << ti, the T <= TMAX with the smallest lane share T / P
+// (ties: the smaller T), packed T | G << 3 | P << 12; magic[d] = ceil(2^32 / d)
+// for the divisions by G and P (d >= 2; d = 1 is taken apart).
+struct SpreadTables {
+  uint32_t plan[3][256];
+  uint32_t magic[257];
+};
+constexpr SpreadTables make_spread_tables() {
+  SpreadTables t{};
+  for (int ti = 0; ti < 3; ++ti) {
+    const int tmax = 1 << ti;
+    for (int r = 1; r < 64 * tmax; ++r) {
+      int bt = 0, bg = 0, bp = 0;
+      for (int T = 1; T <= tmax; ++T) {
+        const int G = (r + T - 1) / T, P = 256 / G;
+        if (P >= 1 && (bt == 0 || T * bp < bt * P)) {
+          bt = T;
+          bg = G;
+          bp = P;
+        }
+      }
+      t.plan[ti][r] = uint32_t(bt) | uint32_t(bg) << 3 | uint32_t(bp) << 12;
+    }
+  }
+  for (int d = 2; d <= 256; ++d) t.magic[d] = uint32_t(((uint64_t(1) << 32) + d - 1) / d);
+  return t;
+}
+__constant__ SpreadTables kSpread = make_spread_tables();
+
+// The spread plan of a step's last chunk: T targets per lane, G groups, P
+// parts of L sources; the parts end at the wake's end, so the first starts
+// `pads` (< P) entries below it. P = 0: no spread chunk this step (no partial
+// chunk, or fewer than P - 1 entries below the wake to hold the pads).
+struct Spread {
+  int T, G, P, L, pads;
+  uint32_t mg;  // magic[G]
+};
+template <int TMAX>
+__device__ inline Spread spread_plan(int NT, int n_w, int head) {
+  Spread s{0, 0, 0, 0, 0, 0u};
+  constexpr int ti = TMAX >= 4 ? 2 : TMAX == 2 ? 1 : 0;
+  const int r = NT & (64 * TMAX - 1);
+  if (r == 0) return s;
+  const uint32_t e = kSpread.plan[ti][r];
+  const int P = static_cast<int>(e >> 12);
+  if (P - 1 > head) return s;
+  s.T = static_cast<int>(e & 7u);
+  s.G = static_cast<int>((e >> 3) & 511u);
+  s.P = P;
+  s.L = P == 1 ? n_w : static_cast<int>(mulhi(static_cast<uint32_t>(n_w + P - 1), kSpread.magic[P]));
+  s.pads = P * s.L - n_w;
+  s.mg = kSpread.magic[s.G];
+  return s;
+}
+
+// The spread chunk at c0: lane gl takes the targets c0 + g + G j (j < T) of
+// group g = gl mod G and the sources of part p = gl / G, [end - (P - p) L,
+// end - (P - p - 1) L) with end = head + n_w; the pads below the wake are
+// zero-strength entries (adding exactly nothing), so every lane runs the same
+// L sources. Lanes past P G keep part 0's range and write nothing. Partials
+// land at red[(p T + j) G + g].
+template <int T, int TILE>
+__device__ void lds_pass_a_spread(const Src32 *src, const Scl32 *pa, Vec2<float> *red,
+                                  int c0, int NT, int head, int n_w, int n_surf,
+                                  const Spread &sp, int gl) {
+  const int pq = sp.G == 1 ? gl : static_cast<int>(mulhi(static_cast<uint32_t>(gl), sp.mg));
+  const int g = gl - pq * sp.G;
+  const bool on = pq < sp.P;
+  const int p = on ? pq : 0;
+  float tx[T], tz[T], sx[T], sz[T], cx[T], cz[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    lds_target<float>(src, c0 + g + sp.G * j, NT, head, n_surf, tx[j], tz[j]);
+    sx[j] = sz[j] = cx[j] = cz[j] = 0.0f;
+  }
+  const Scl32 *part = pa + (head + n_w - (sp.P - p) * sp.L);
+  accumulate<float, T, TILE>(part, 0, sp.L, tx, tz, 0.0f, sx, sz, cx, cz, true);
+  if (on) {
+#pragma unroll
+    for (int j = 0; j < T; ++j)
+      red[(p * T + j) * sp.G + g] = Vec2<float>{sx[j] + cx[j], sz[j] + cz[j]};
+  }
+}
+
 // Issue priority of this wave for step n. Several rollouts share a CU, and
 // the sequencer issues from the oldest wave first, so with equal priorities
 // the first-dispatched workgroup runs at almost solo speed and the last one
@@ -1024,7 +1139,8 @@ __device__ inline void stage_inverses(const KArgs &a, double *kinv, int tid, int
 // sources into NW contiguous slices (one per wave) and adds the slices in
 // FP64 in wave order. MINW: waves per SIMD the register budget must allow.
 template <typename R, int TMAX, int MINW, int NW, int TILE, bool EXT>
-__global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Queue qu) {
+__global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs args, Queue qu) {
+  const KArgs &a = args;
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
   extern __shared__ __align__(32) unsigned char lds[];
@@ -1052,12 +1168,16 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
     const int k = claim(qu, sh, tid, fallback);
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr, n_surf)) continue;
+    if (!setup(fresh_args(args), sh, src, scl, k, opaque_tid(tid), kThr, n_surf)) continue;
     __syncthreads();
 
-    for (int n = 0; n < a.H; ++n) {
+    const int H = a.H;
+    for (int n = 0; n < H; ++n) {
+      // the arguments as this step reads them (see fresh_args); each section
+      // below takes its own copy
+      const KArgs &a = fresh_args(args);
       if (n == 0) {
-        if (tid == 0) prologue<R, EXT>(a, sh, src, scl, 0);
+        if (tid == 0) prologue<R, EXT>(fresh_args(args), sh, src, scl, 0);
         __syncthreads();
       }
       rotate_priority(sh.slot, n);
@@ -1072,6 +1192,16 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
                       px, pz);
         src[head - n_surf + tid] = Src{px, pz, R(0), R(0)};
       }
+      // the plan of this step's last chunk if it is spread, and its pads:
+      // zero-strength entries of the scaled copy just below the wake (dead
+      // entries: the wake only moves up)
+      Spread sp{0, 0, 0, 0, 0, 0u};
+      if constexpr (SCL) {
+        sp = spread_plan<TMAX>(__builtin_amdgcn_readfirstlane(NT),
+                               __builtin_amdgcn_readfirstlane(n_w),
+                               __builtin_amdgcn_readfirstlane(head));
+        if (tid < sp.pads) scl[head - sp.pads + tid] = Scl32{0.0f, 0.0f, 0.0f, INFINITY};
+      }
       __syncthreads();
       // this step's control, loaded now so its latency hides behind pass A
       double u_m = 0.0, u_e = 0.0;
@@ -1082,8 +1212,51 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
 
       const int s_lo = head + (n_w * wave) / NW;
       const int s_hi = head + (n_w * (wave + 1)) / NW;
+      // pass-A velocity of target tt (surface point, or wake entry)
+      auto store_velocity = [&](int tt, double vx, double vz) {
+        if (tt < n_surf) {
+          vsurf[tt] = make_double2(vx, vz);
+        } else {
+          const int i = head + tt - n_surf;
+          // the self term of a scaled pair: the small class removes it in
+          // pass B; staged chunks of the large class here (tails are unscaled)
+          if constexpr (sizeof(R) == 4 && !SCL)
+            remove_self(src[i].x, src[i].z, pass_a_source(src[i], float(a.r_core)), vx, vz);
+          vel[i] = Vec2<R>{R(vx), R(vz)};
+        }
+      };
       for (int c0 = 0; c0 < NT;) {
         const int rem = NT - c0;
+        if constexpr (SCL) {
+          if (sp.P > 0 && rem < 64 * TMAX) {
+            // the last chunk, spread over every lane
+            switch (sp.T) {
+              case 1: lds_pass_a_spread<1, TILE>(src, pa, red, c0, NT, head, n_w, n_surf, sp, tid); break;
+              case 2: if constexpr (TMAX >= 2) lds_pass_a_spread<2, TILE>(src, pa, red, c0, NT, head, n_w, n_surf, sp, tid); break;
+              case 3: if constexpr (TMAX >= 4) lds_pass_a_spread<3, TILE>(src, pa, red, c0, NT, head, n_w, n_surf, sp, tid); break;
+              default: if constexpr (TMAX >= 4) lds_pass_a_spread<4, TILE>(src, pa, red, c0, NT, head, n_w, n_surf, sp, tid); break;
+            }
+            __syncthreads();
+            // lane g adds its groups' parts in FP64 in part order
+            if (tid < sp.G) {
+              for (int j = 0; j < sp.T; ++j) {
+                const int i = tid + sp.G * j;
+                if (i < rem) {
+                  const Vec2<R> r0 = red[j * sp.G + tid];
+                  double vx = double(r0.x), vz = double(r0.z);
+                  for (int p = 1; p < sp.P; ++p) {
+                    const Vec2<R> r = red[(p * sp.T + j) * sp.G + tid];
+                    vx += double(r.x);
+                    vz += double(r.z);
+                  }
+                  store_velocity(c0 + i, vx, vz);
+                }
+              }
+            }
+            __syncthreads();
+            break;
+          }
+        }
         // largest chunk of 4, 3, 2 or 1 targets per lane that is at least 3/4
         // full (fewer chunks, barriers and cross-wave combines for a few idle
         // target slots; the 3-target chunk keeps the last chunk of a step
@@ -1094,13 +1267,13 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
         else if (TMAX >= 2 && 48 * 2 <= rem) T = 2;
         const int tail = rem < 32 ? rem : 0;  // tails of 32..63 keep a lane each
         if (tail) {
-          lds_pass_a_tail<R, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
+          lds_pass_a_tail<R, NW, TILE>(fresh_args(args), sh, src, pa, red, c0, NT, head, s_lo, s_hi, tail, lane, wave);
         } else {
           switch (T) {
-            case 1: lds_pass_a_chunk<R, 1, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            case 3: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 3, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
-            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW, TILE>(a, sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 1: lds_pass_a_chunk<R, 1, NW, TILE>(fresh_args(args), sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 2: if constexpr (TMAX >= 2) lds_pass_a_chunk<R, 2, NW, TILE>(fresh_args(args), sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            case 3: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 3, NW, TILE>(fresh_args(args), sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
+            default: if constexpr (TMAX >= 4) lds_pass_a_chunk<R, 4, NW, TILE>(fresh_args(args), sh, src, pa, red, c0, NT, head, s_lo, s_hi, lane, wave); break;
           }
         }
         __syncthreads();
@@ -1119,15 +1292,10 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
             }
           }
           const int tt = c0 + t;
-          if (tt < n_surf) {
-            vsurf[tt] = make_double2(vx, vz);
+          if (tail && tt >= n_surf && sizeof(R) == 4 && !SCL) {
+            vel[head + tt - n_surf] = Vec2<R>{R(vx), R(vz)};  // unscaled: no self term
           } else {
-            const int i = head + tt - n_surf;
-            // the self term of a scaled pair: the small class removes it in
-            // pass B; staged chunks of the large class here (tails are unscaled)
-            if constexpr (sizeof(R) == 4 && !SCL)
-              if (!tail) remove_self(src[i].x, src[i].z, pass_a_source(src[i], float(a.r_core)), vx, vz);
-            vel[i] = Vec2<R>{R(vx), R(vz)};
+            store_velocity(tt, vx, vz);
           }
         }
         __syncthreads();
@@ -1135,16 +1303,16 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs a, Que
       }
 
       if (wave == 0)
-        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
+        solve_section(fresh_args(args), sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
                       EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
-      pass_b(a, sh, src, scl, vel, k, n == a.H - 1, head, n_w + n_shed, n_w, tid, kThr,
+      pass_b(fresh_args(args), sh, src, scl, vel, k, n == H - 1, head, n_w + n_shed, n_w, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(fresh_args(args), sh, src, scl, k, n, n_w);
       __syncthreads();
     }
-    finish(a, sh, src, k, opaque_tid(tid), kThr);
+    finish(fresh_args(args), sh, src, k, opaque_tid(tid), kThr);
   }
 }
 
@@ -1191,7 +1359,8 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
 // blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
 // or, with a queue, claims them in planned order.
 template <typename R, int TMAX, int NW, int TILE, bool EXT>
-__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Queue qu) {
+__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs args, Queue qu) {
+  const KArgs &a = args;
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
   extern __shared__ __align__(32) unsigned char lds[];
@@ -1221,11 +1390,13 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
     }
     if (k < 0) break;
     __syncthreads();
-    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr, 0)) continue;
+    if (!setup(fresh_args(args), sh, src, scl, k, opaque_tid(tid), kThr, 0)) continue;
     __syncthreads();
-    for (int n = 0; n < a.H; ++n) {
+    const int H = a.H;
+    for (int n = 0; n < H; ++n) {
+      const KArgs &a = fresh_args(args);  // this step's reads (see fresh_args)
       if (n == 0) {
-        if (tid == 0) prologue<R, EXT>(a, sh, src, scl, 0);
+        if (tid == 0) prologue<R, EXT>(fresh_args(args), sh, src, scl, 0);
         __syncthreads();
       }
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
@@ -1241,24 +1412,24 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
         int T = TMAX;
         while (T > 1 && 64 * NW * T > rem) T >>= 1;
         switch (T) {
-          case 1: stream_pass_a_round<R, 1, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
-          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
-          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 1: stream_pass_a_round<R, 1, NW, TILE>(fresh_args(args), sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW, TILE>(fresh_args(args), sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW, TILE>(fresh_args(args), sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
         }
         c0 += 64 * NW * T;
       }
       __syncthreads();
       if (wave == 0)
-        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
+        solve_section(fresh_args(args), sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
                       EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
-      pass_b(a, sh, src, scl, vel, k, n == a.H - 1, head, n_w + n_shed, n_w, tid, kThr,
+      pass_b(fresh_args(args), sh, src, scl, vel, k, n == H - 1, head, n_w + n_shed, n_w, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(fresh_args(args), sh, src, scl, k, n, n_w);
       __syncthreads();
     }
-    finish(a, sh, src, k, opaque_tid(tid), kThr);
+    finish(fresh_args(args), sh, src, k, opaque_tid(tid), kThr);
   }
 }
 

@@ -23,6 +23,11 @@ def build():
         # dynamic LDS becomes the emulated block's buffer
         s = re.sub(r"extern __shared__ __align__\(\d+\) unsigned char (\w+)\[\];",
                    r"unsigned char *\1 = emu_blk->dyn;", s)
+        # kernel arguments are the kernel function's own parameter (no
+        # kernarg segment on the CPU)
+        s = re.sub(r"__device__ inline const KArgs &fresh_args\(const KArgs &\) \{.*?\n\}",
+                   "__device__ inline const KArgs &fresh_args(const KArgs &a) { return a; }",
+                   s, flags=re.S)
         open(os.path.join(src_dir, f), "w").write(s)
     cmd = ["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-fvisibility=hidden",
            "-I", HERE, "-I", os.path.join(ROOT, "include"), "-I", src_dir, "-o", LIB + ".tmp",

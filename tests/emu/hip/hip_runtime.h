@@ -37,6 +37,7 @@ using std::isnan;
 #define __launch_bounds__(...)
 #define __align__(n) alignas(n)
 #define __shared__ static
+#define __constant__
 #define HIP_SYMBOL(x) (&(x))
 
 typedef int hipError_t;
