@@ -1359,8 +1359,7 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
 // blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
 // or, with a queue, claims them in planned order.
 template <typename R, int TMAX, int NW, int TILE, bool EXT>
-__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs args, Queue qu) {
-  const KArgs &a = args;
+__global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Queue qu) {
   using Src = typename SrcOf<R>::type;
   constexpr int kThr = 64 * NW;
   extern __shared__ __align__(32) unsigned char lds[];
@@ -1390,13 +1389,11 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs args, 
     }
     if (k < 0) break;
     __syncthreads();
-    if (!setup(fresh_args(args), sh, src, scl, k, opaque_tid(tid), kThr, 0)) continue;
+    if (!setup(a, sh, src, scl, k, opaque_tid(tid), kThr, 0)) continue;
     __syncthreads();
-    const int H = a.H;
-    for (int n = 0; n < H; ++n) {
-      const KArgs &a = fresh_args(args);  // this step's reads (see fresh_args)
+    for (int n = 0; n < a.H; ++n) {
       if (n == 0) {
-        if (tid == 0) prologue<R, EXT>(fresh_args(args), sh, src, scl, 0);
+        if (tid == 0) prologue<R, EXT>(a, sh, src, scl, 0);
         __syncthreads();
       }
       const int head = sh.head, n_w = sh.n_w, n_shed = sh.n_shed;
@@ -1412,24 +1409,24 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs args, 
         int T = TMAX;
         while (T > 1 && 64 * NW * T > rem) T >>= 1;
         switch (T) {
-          case 1: stream_pass_a_round<R, 1, NW, TILE>(fresh_args(args), sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
-          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW, TILE>(fresh_args(args), sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
-          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW, TILE>(fresh_args(args), sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 1: stream_pass_a_round<R, 1, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
+          default: if constexpr (TMAX >= 4) stream_pass_a_round<R, 4, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
         }
         c0 += 64 * NW * T;
       }
       __syncthreads();
       if (wave == 0)
-        solve_section(fresh_args(args), sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
+        solve_section(a, sh, src, vel, vsurf, kinv, k, n, head, n_w, lane,
                       EXT ? u_m + u_e + sh.u_fb : u_m + u_e);
       __syncthreads();
-      pass_b(fresh_args(args), sh, src, scl, vel, k, n == H - 1, head, n_w + n_shed, n_w, tid, kThr,
+      pass_b(a, sh, src, scl, vel, k, n == a.H - 1, head, n_w + n_shed, n_w, tid, kThr,
              reinterpret_cast<double2 *>(lds + a.off_red));
       __syncthreads();
-      if (tid == 0) epilogue<R, EXT>(fresh_args(args), sh, src, scl, k, n, n_w);
+      if (tid == 0) epilogue<R, EXT>(a, sh, src, scl, k, n, n_w);
       __syncthreads();
     }
-    finish(fresh_args(args), sh, src, k, opaque_tid(tid), kThr);
+    finish(a, sh, src, k, opaque_tid(tid), kThr);
   }
 }
 
