@@ -89,6 +89,7 @@ struct KArgs {
   double alpha_crit;
   double dt, chord, shed_frac, r_core, decay, rho, span, grav, mass, inertia;
   double inv_dt, inv_lb, inv_mass, inv_inertia;  // host reciprocals
+  double lb;                                      // panel length c / N_b (host)
   double l_body, l_wing, l_elev, s_elev;
   double x_goal[7], q_diag[7];
   const double *g0, *gb0, *wx, *wz, *wg, *u_mean, *u_eps, *kinv_t;
@@ -116,7 +117,7 @@ template <typename R> struct Shared {
   Bound<R> bnd[kMaxBound];
   R shed_g[2];
   double gb_prev[kMaxBound];
-  double bvec[kMaxBound + 2];
+  double bvec[kMaxBound + 8];  // b of the solve, zero-padded to a multiple of 8
   int head, n_w, status;
   int claimed;  // rollout claimed from the work queue
   int slot;     // issue-priority slot of this workgroup (see rotate_priority)
@@ -406,7 +407,7 @@ __device__ inline void target_pos(const KArgs &a, const Shared<R> &sh,
   px = pz = R(0);
   if (t >= NT) return;
   if (t < n_surf) {
-    surface_point(sh, t, a.nb, R(a.chord / a.nb), R(a.shed_frac * a.chord),
+    surface_point(sh, t, a.nb, R(a.lb), R(a.shed_frac * a.chord),
                   R(a.chord), px, pz);
   } else {
     const auto v = src[head + t - n_surf];
@@ -414,6 +415,10 @@ __device__ inline void target_pos(const KArgs &a, const Shared<R> &sh,
     pz = v.z;
   }
 }
+
+// Sine and cosine with one argument reduction.
+__device__ inline void sin_cos(float x, float &s, float &c) { sincosf(x, &s, &c); }
+__device__ inline void sin_cos(double x, double &s, double &c) { sincos(x, &s, &c); }
 
 // Segment a-b against the chord rectangle inflated by 2 % of chord opposite
 // the normal (Sec. V), by Liang-Barsky clipping in plate coordinates.
@@ -447,7 +452,8 @@ __device__ bool hits_plate(const Shared<R> &sh, double c, double ax, double az,
 template <typename R>
 __device__ void geometry(const KArgs &a, Shared<R> &sh) {
   const R th = sh.g[2], thd = sh.g[6], lw = R(a.l_wing);
-  const R ct = cos(th), st = sin(th);
+  R ct, st;
+  sin_cos(th, st, ct);
   const R hc = R(0.5 * a.chord), ds = R(a.shed_frac * a.chord);
   sh.ct = ct;
   sh.st = st;
@@ -592,7 +598,7 @@ __device__ __forceinline__ void solve_section(
   const int mode = __builtin_amdgcn_readfirstlane(sh.mode_step);
   const int S = system_size(nb, mode), c0 = first_row(mode);
   if (a.gate && mode == VPM_SHED_TE) kinv += a.S * a.S;
-  const double dt = a.dt, lb = a.chord / nb;
+  const double dt = a.dt, lb = a.lb;
   const R dtr = R(dt);
   double sg = 0.0;
   for (int q = lane; q < n_w; q += 64) sg += double(src[head + q].g);
@@ -612,10 +618,12 @@ __device__ __forceinline__ void solve_section(
     const double vz = vw.y - xwdz - thd * (px - xwx);
     return -(vx * enx + vz * enz);
   };
-  // b goes through LDS (broadcast reads cost no VALU issue slots); the
-  // inverse and b are read 8 entries at a time
-  if (lane < S) sh.bvec[lane] = rhs(lane);
-  if (lane + 64 < S) sh.bvec[lane + 64] = rhs(lane + 64);
+  // b goes through LDS (broadcast reads cost no VALU issue slots), zero
+  // up to the next multiple of 8; the inverse and b are read 8 entries at a
+  // time
+  const int s8 = (S + 7) & ~7;
+  if (lane < s8) sh.bvec[lane] = rhs(lane);
+  if (lane + 64 < s8) sh.bvec[lane + 64] = rhs(lane + 64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -627,8 +635,8 @@ __device__ __forceinline__ void solve_section(
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int j = j0 + q < S ? j0 + q : S - 1;
-      kv[q] = kinv[j * S + i0];
-      bj[q] = j0 + q < S ? sh.bvec[j] : 0.0;
+      kv[q] = kinv[j * S + i0];  // rows past S repeat row S - 1 (times b = 0)
+      bj[q] = sh.bvec[j0 + q];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) gam0 += kv[q] * bj[q];
@@ -683,7 +691,9 @@ __device__ __forceinline__ void solve_section(
     const R xd = sh.g[4], zd = sh.g[5], thr = sh.g[6];
     const R u = R(u_n);
     const R l = R(a.l_body), le = R(a.l_elev);
-    const R ct = sh.ct, st = sh.st, ctp = cos(th + ph), stp = sin(th + ph);
+    const R ct = sh.ct, st = sh.st;
+    R ctp, stp;
+    sin_cos(th + ph, stp, ctp);
     const R xe = x - l * ct - le * ctp, ze = z - l * st - le * stp;
     const R xed = xd + l * thr * st + le * (thr + u) * stp;
     const R zed = zd - l * thr * ct - le * (thr + u) * ctp;
@@ -1188,7 +1198,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs args, 
       // vortex (the wake starts at n_surf and only moves up as it merges)
       if (tid < n_surf) {
         R px, pz;
-        surface_point(sh, tid, a.nb, R(a.chord / a.nb), R(a.shed_frac * a.chord), R(a.chord),
+        surface_point(sh, tid, a.nb, R(a.lb), R(a.shed_frac * a.chord), R(a.chord),
                       px, pz);
         src[head - n_surf + tid] = Src{px, pz, R(0), R(0)};
       }
@@ -1957,6 +1967,7 @@ int launch_rollout(vpm_ctx *ctx, const vpm_params *p, const vpm_batch_in *in,
   a.inertia = p->inertia;
   a.inv_dt = 1.0 / in->dt;
   a.inv_lb = p->n_bound / p->chord;
+  a.lb = p->chord / p->n_bound;
   a.inv_mass = 1.0 / p->mass;
   a.inv_inertia = 1.0 / p->inertia;
   a.l_body = p->l_body;
