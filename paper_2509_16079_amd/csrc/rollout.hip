@@ -444,6 +444,11 @@ __device__ bool hits_plate(const Shared<R> &sh, double c, double ax, double az,
   const double tx = sh.et[0], tz = sh.et[1], nx = sh.en[0], nz = sh.en[1];
   double sa = (ax - lx) * tx + (az - lz) * tz, ha = (ax - lx) * nx + (az - lz) * nz;
   double sb = (bx - lx) * tx + (bz - lz) * tz, hb = (bx - lx) * nx + (bz - lz) * nz;
+  // both ends on the far side of one slab face: no crossing (the common
+  // case, decided without the clipping divisions)
+  if ((sa < 0.0 && sb < 0.0) || (sa > c && sb > c) || (ha > 0.0 && hb > 0.0) ||
+      (ha < -0.02 * c && hb < -0.02 * c))
+    return false;
   double u0 = 0.0, u1 = 1.0;
   if (!clip_slab(sa, sb - sa, 0.0, c, u0, u1)) return false;
   return clip_slab(ha, hb - ha, -0.02 * c, 0.0, u0, u1);
