@@ -368,18 +368,20 @@ __device__ inline void accumulate_staged(const Src32 *__restrict__ src, Scl32 *s
   }
 }
 
+// Chord coordinate (from the leading edge) of surface point t: collocation
+// points, bound vortices, LEV and TEV release points.
+template <typename R>
+__device__ inline R surface_s(int t, int nb, R lb, R ds, R c) {
+  if (t <= nb) return R(t) * lb;                                  // collocation, LE to TE
+  if (t < 2 * nb + 1) return (R(t - nb - 1) + R(0.5)) * lb;       // bound
+  if (t == 2 * nb + 1) return -ds;                                // LEV release point
+  return c + ds;                                                  // TEV release point
+}
+
 template <typename R>
 __device__ inline void surface_point(const Shared<R> &sh, int t, int nb, R lb,
                                      R ds, R c, R &px, R &pz) {
-  R s;
-  if (t <= nb)
-    s = R(t) * lb;  // collocation, LE to TE
-  else if (t < 2 * nb + 1)
-    s = (R(t - nb - 1) + R(0.5)) * lb;  // bound
-  else if (t == 2 * nb + 1)
-    s = -ds;  // LEV release point
-  else
-    s = c + ds;  // TEV release point
+  const R s = surface_s(t, nb, lb, ds, c);
   px = sh.le[0] + s * sh.et[0];
   pz = sh.le[1] + s * sh.et[1];
 }
@@ -1176,6 +1178,8 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs args, 
   // it are counted in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_surf = 2 * a.nb + 3;
+  // this thread's surface point's chord coordinate (threads below n_surf)
+  const R s_surf = surface_s(tid, a.nb, R(a.lb), R(a.shed_frac * a.chord), R(a.chord));
   stage_inverses(a, kinv, tid, kThr);
   if (tid == 0) sh.slot = simd_id();
   int fallback = blockIdx.x;
@@ -1201,12 +1205,9 @@ __global__ __launch_bounds__(64 * NW, MINW) void rollout_lds_kernel(KArgs args, 
       // the step's surface points (collocation, bound, release) as pass-A
       // targets in the n_surf entries below the wake, which hold no live
       // vortex (the wake starts at n_surf and only moves up as it merges)
-      if (tid < n_surf) {
-        R px, pz;
-        surface_point(sh, tid, a.nb, R(a.lb), R(a.shed_frac * a.chord), R(a.chord),
-                      px, pz);
-        src[head - n_surf + tid] = Src{px, pz, R(0), R(0)};
-      }
+      if (tid < n_surf)
+        src[head - n_surf + tid] =
+            Src{sh.le[0] + s_surf * sh.et[0], sh.le[1] + s_surf * sh.et[1], R(0), R(0)};
       // the plan of this step's last chunk if it is spread, and its pads:
       // zero-strength entries of the scaled copy just below the wake (dead
       // entries: the wake only moves up)

@@ -132,15 +132,19 @@ template <class T> inline T emu_exchange(T v, int src) {
 template <class T> inline T __shfl(T v, int src, int = 64) { return emu_exchange(v, src); }
 template <class T> inline T __shfl_xor(T v, int m, int = 64) { return emu_exchange(v, (int)(threadIdx.x & 63) ^ m); }
 #define __builtin_amdgcn_readfirstlane(v) emu_exchange((v), 0)
-// DPP within a 16-lane row: quad_perm and row_ror (the controls the kernels use)
-inline int emu_dpp(int v, int ctrl) {
-  const int l = threadIdx.x & 63;
+// DPP: quad_perm, row_ror, row_bcast:15 and row_bcast:31 (the controls the
+// kernels use); rows outside the row mask keep `old`
+inline int emu_dpp(int old, int v, int ctrl, int row_mask) {
+  const int l = threadIdx.x & 63, row = l >> 4;
   int src = l;
   if (ctrl < 0x100) src = (l & ~3) + ((ctrl >> (2 * (l & 3))) & 3);
   else if (ctrl > 0x120 && ctrl < 0x130) src = (l & ~15) + (((l & 15) - (ctrl - 0x120)) & 15);
-  return emu_exchange(v, src);
+  else if (ctrl == 0x142) src = row > 0 ? 16 * row - 1 : l;
+  else if (ctrl == 0x143) src = 31;
+  const int r = emu_exchange(v, src);
+  return (row_mask >> row) & 1 ? r : old;
 }
-#define __builtin_amdgcn_update_dpp(old, v, ctrl, rm, bm, bc) emu_dpp((v), (ctrl))
+#define __builtin_amdgcn_update_dpp(old, v, ctrl, rm, bm, bc) emu_dpp((old), (v), (ctrl), (rm))
 #define __builtin_amdgcn_readlane(v, j) emu_exchange((v), (j))
 inline long long __double_as_longlong(double d) { long long r; memcpy(&r, &d, 8); return r; }
 inline double __longlong_as_double(long long v) { double r; memcpy(&r, &v, 8); return r; }
