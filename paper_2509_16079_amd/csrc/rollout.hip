@@ -1371,6 +1371,68 @@ __device__ void stream_pass_a_round(const KArgs &a, const Shared<R> &sh,
   }
 }
 
+// A source that adds exactly nothing (zero strength) in pass-A form.
+__device__ inline Scl32 zero_pass_a(Scl32) { return Scl32{0.0f, 0.0f, 0.0f, INFINITY}; }
+__device__ inline Src64 zero_pass_a(Src64) { return Src64{0.0, 0.0, 0.0, 0.0}; }
+
+// The last round of a step when it holds r < 64 NW targets: W = ceil(r / 64)
+// waves hold one target per lane, and the P = NW / W groups of W waves take
+// one of P equal source parts of L = ceil(n_w / P) each. Every tile step
+// stages P slices of kStreamTile / P sources, slice i from part i (entries
+// past the wake are zero sources), and each wave sums only its part's slice,
+// so the round costs 1 / P of a full pass over the sources instead of a
+// whole pass for a partly idle set of lanes. The part sums are added in FP64
+// in part order by the first group, through the tile buffer.
+template <typename R, int NW, int TILE>
+__device__ void stream_pass_a_spread(const KArgs &a, const Shared<R> &sh,
+                                     const typename SrcOf<R>::type *src,
+                                     typename PassAOf<R>::type *tile, Vec2<R> *vel,
+                                     double2 *vsurf, int c0, int NT, int head, int n_w,
+                                     int tid, int lane, int wave, int W, int P) {
+  using PA = typename PassAOf<R>::type;
+  const int n_surf = 2 * a.nb + 3;
+  const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
+  const int TS = kStreamTile / P;     // sources of one part per tile step
+  const int L = (n_w + P - 1) / P;    // sources per part (the last may run past the wake)
+  const int p = wave / W;             // this wave's part (p == P: an idle wave)
+  const int slot = (wave - p * W) * 64 + lane;
+  const int t = c0 + slot;
+  R tx[1], tz[1], sx[1] = {R(0)}, sz[1] = {R(0)}, cx[1] = {R(0)}, cz[1] = {R(0)};
+  target_pos(a, sh, src, t, NT, head, tx[0], tz[0]);
+  for (int s0 = 0; s0 < L; s0 += TS) {
+    const int cnt = min(TS, L - s0);
+    for (int q = tid; q < P * TS; q += 64 * NW) {
+      const int pp = q / TS, i = q - pp * TS;
+      const int g = pp * L + s0 + i;  // source index (part pp, this step's slice)
+      tile[q] = i < cnt && g < n_w ? pass_a_source(src[head + g], rc) : zero_pass_a(PA{});
+    }
+    __syncthreads();
+    if (p < P) accumulate<R, 1, TILE>(tile + p * TS, 0, cnt, tx, tz, rc4, sx, sz, cx, cz, s0 == 0);
+    __syncthreads();
+  }
+  double2 *part = reinterpret_cast<double2 *>(tile);  // P W 64 entries fit the tile
+  if (p < P)
+    part[p * W * 64 + slot] =
+        make_double2(double(sx[0]) + double(cx[0]), double(sz[0]) + double(cz[0]));
+  __syncthreads();
+  if (p == 0 && t < NT) {
+    double vx = part[slot].x, vz = part[slot].y;
+    for (int q = 1; q < P; ++q) {
+      const double2 d = part[q * W * 64 + slot];
+      vx += d.x;
+      vz += d.y;
+    }
+    if (t < n_surf) {
+      vsurf[t] = make_double2(vx, vz);
+    } else {
+      const int i = head + t - n_surf;
+      if constexpr (sizeof(R) == 4) remove_self(tx[0], tz[0], pass_a_source(src[i], rc), vx, vz);
+      vel[i] = Vec2<R>{R(vx), R(vz)};
+    }
+  }
+  __syncthreads();  // the tile buffer is staged again by the next round
+}
+
 // Persistent: each workgroup keeps its rollout's wake in workspace slot
 // blockIdx.x (a.cap sources and velocities) and walks rollouts b, b + G, ...
 // or, with a queue, claims them in planned order.
@@ -1424,6 +1486,13 @@ __global__ __launch_bounds__(64 * NW, 1) void rollout_stream_kernel(KArgs a, Que
         const int rem = NT - c0;
         int T = TMAX;
         while (T > 1 && 64 * NW * T > rem) T >>= 1;
+        const int W = (rem + 63) / 64;
+        if (T == 1 && 2 * W <= NW) {
+          // a ragged last round: spread over source parts
+          stream_pass_a_spread<R, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid,
+                                            lane, wave, W, NW / W);
+          break;
+        }
         switch (T) {
           case 1: stream_pass_a_round<R, 1, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
           case 2: if constexpr (TMAX >= 2) stream_pass_a_round<R, 2, NW, TILE>(a, sh, src, tile, vel, vsurf, c0, NT, head, n_w, tid, lane, wave); break;
