@@ -27,8 +27,9 @@
 //  - rollout_stream_kernel (NW waves, persistent): the wake lives in a
 //    per-workgroup slot of a global workspace; 1024-source tiles are staged
 //    cooperatively through LDS and every wave walks all of them for its own
-//    targets, so each target sums its sources in strict FIFO order. It
-//    serves wakes too large for LDS (tens of thousands of vortices).
+//    targets, in FIFO order; a ragged last round instead gives each group
+//    of waves one part of the sources and adds the parts in FP64 in order.
+//    It serves wakes too large for LDS (tens of thousands of vortices).
 //
 // The N^2 work is pure VALU: per regularised pair 7 FP32 ops + 1 v_rsq_f32 on
 // sources pre-scaled by 1/Gamma (FP32), 8 + 1 on unscaled sources (FP64, and
