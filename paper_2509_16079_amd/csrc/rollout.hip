@@ -305,6 +305,23 @@ __device__ inline void accumulate(const S *__restrict__ src,
   }
 }
 
+// Sources [s_lo, s_hi), at most one tile of them, onto the T targets of this
+// lane: a single tile is never folded, so its plain sums are the totals and
+// the compensation terms (all zero) are neither kept nor added.
+template <typename R, int T, typename S>
+__device__ inline void accumulate_one_tile(const S *__restrict__ src, int s_lo, int s_hi,
+                                           const R (&tx)[T], const R (&tz)[T], R rc4,
+                                           R (&sx)[T], R (&sz)[T]) {
+#pragma unroll
+  for (int j = 0; j < T; ++j) sx[j] = sz[j] = R(0);
+#pragma unroll 4
+  for (int q = s_lo; q < s_hi; ++q) {
+    const S v = src[q];
+#pragma unroll
+    for (int j = 0; j < T; ++j) pair_term(tx[j], tz[j], v, rc4, sx[j], sz[j]);
+  }
+}
+
 // The thread index, opaque to the compiler at this point: addresses that
 // setup and finish derive from it are then computed per rollout instead of
 // being hoisted out of the persistent rollout loop, where these per-lane
@@ -993,16 +1010,23 @@ __device__ void lds_pass_a_chunk(const KArgs &a, const Shared<R> &sh,
   const R rc = R(a.r_core), rc4 = rc * rc * rc * rc;
   R tx[T], tz[T], sx[T], sz[T], cx[T], cz[T];
 #pragma unroll
-  for (int j = 0; j < T; ++j) {
-    lds_target(src, c0 + lane + 64 * j, NT, head, 2 * a.nb + 3, tx[j], tz[j]);
-    sx[j] = sz[j] = cx[j] = cz[j] = R(0);
+  for (int j = 0; j < T; ++j) lds_target(src, c0 + lane + 64 * j, NT, head, 2 * a.nb + 3, tx[j], tz[j]);
+  Vec2<R> *out = red + wave * 64 * T;
+  if constexpr (!std::is_same_v<S, Src32>) {
+    if (s_hi - s_lo <= TILE) {  // uniform: one tile
+      accumulate_one_tile<R, T>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz);
+#pragma unroll
+      for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j], sz[j]};
+      return;
+    }
   }
+#pragma unroll
+  for (int j = 0; j < T; ++j) sx[j] = sz[j] = cx[j] = cz[j] = R(0);
   if constexpr (std::is_same_v<S, Src32>)
     accumulate_staged<T, TILE>(pa, reinterpret_cast<Scl32 *>(red + wave * 64 * T), s_lo, s_hi,
                                rc, lane, tx, tz, sx, sz, cx, cz);
   else
     accumulate<R, T, TILE>(pa, s_lo, s_hi, tx, tz, rc4, sx, sz, cx, cz, true);
-  Vec2<R> *out = red + wave * 64 * T;
 #pragma unroll
   for (int j = 0; j < T; ++j) out[lane + 64 * j] = Vec2<R>{sx[j] + cx[j], sz[j] + cz[j]};
 }
@@ -1111,11 +1135,18 @@ __device__ void lds_pass_a_spread(const Src32 *src, const Scl32 *pa, Vec2<float>
   const int p = on ? pq : 0;
   float tx[T], tz[T], sx[T], sz[T], cx[T], cz[T];
 #pragma unroll
-  for (int j = 0; j < T; ++j) {
-    lds_target<float>(src, c0 + g + sp.G * j, NT, head, n_surf, tx[j], tz[j]);
-    sx[j] = sz[j] = cx[j] = cz[j] = 0.0f;
-  }
+  for (int j = 0; j < T; ++j) lds_target<float>(src, c0 + g + sp.G * j, NT, head, n_surf, tx[j], tz[j]);
   const Scl32 *part = pa + (head + n_w - (sp.P - p) * sp.L);
+  if (sp.L <= TILE) {  // uniform: one tile
+    accumulate_one_tile<float, T>(part, 0, sp.L, tx, tz, 0.0f, sx, sz);
+    if (on) {
+#pragma unroll
+      for (int j = 0; j < T; ++j) red[(p * T + j) * sp.G + g] = Vec2<float>{sx[j], sz[j]};
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < T; ++j) sx[j] = sz[j] = cx[j] = cz[j] = 0.0f;
   accumulate<float, T, TILE>(part, 0, sp.L, tx, tz, 0.0f, sx, sz, cx, cz, true);
   if (on) {
 #pragma unroll
