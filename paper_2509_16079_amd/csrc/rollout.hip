@@ -625,9 +625,15 @@ __device__ __forceinline__ void solve_section(
   if (a.gate && mode == VPM_SHED_TE) kinv += a.S * a.S;
   const double dt = a.dt, lb = a.lb;
   const R dtr = R(dt);
-  double sg = 0.0;
-  for (int q = lane; q < n_w; q += 64) sg += double(src[head + q].g);
-  const double sum_gw = kTwoPi * wave_sum(sg);
+  // Kelvin sum over the wake, two partial sums in flight
+  double sg = 0.0, sg1 = 0.0;
+  int qk = lane;
+  for (; qk + 64 < n_w; qk += 128) {
+    sg += double(src[head + qk].g);
+    sg1 += double(src[head + qk + 64].g);
+  }
+  if (qk < n_w) sg += double(src[head + qk].g);
+  const double sum_gw = kTwoPi * wave_sum(sg + sg1);
   const double lex = sh.le[0], lez = sh.le[1], etx = sh.et[0], etz = sh.et[1];
   const double enx = sh.en[0], enz = sh.en[1];
   const double xwx = sh.xw[0], xwz = sh.xw[1], thd = sh.g[6];
@@ -645,7 +651,7 @@ __device__ __forceinline__ void solve_section(
   };
   // b goes through LDS (broadcast reads cost no VALU issue slots), zero
   // up to the next multiple of 8; the inverse and b are read 8 entries at a
-  // time
+  // time, into four partial sums so that the FMA chain is a quarter as long
   const int s8 = (S + 7) & ~7;
   if (lane < s8) sh.bvec[lane] = rhs(lane);
   if (lane + 64 < s8) sh.bvec[lane + 64] = rhs(lane + 64);
@@ -653,7 +659,7 @@ __device__ __forceinline__ void solve_section(
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // Gamma_S = K^-1 b (Eq. 11): lane i owns rows i and i + 64
-  double gam0 = 0.0, gam1 = 0.0;
+  double p0[4] = {0.0, 0.0, 0.0, 0.0}, gam1 = 0.0;
   const int i0 = lane < S ? lane : 0, i1 = lane + 64 < S ? lane + 64 : 0;
   for (int j0 = 0; j0 < S; j0 += 8) {
     double kv[8], bj[8];
@@ -664,7 +670,7 @@ __device__ __forceinline__ void solve_section(
       bj[q] = sh.bvec[j0 + q];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) gam0 += kv[q] * bj[q];
+    for (int q = 0; q < 8; ++q) p0[q & 3] += kv[q] * bj[q];
     if (S > 64) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -673,6 +679,7 @@ __device__ __forceinline__ void solve_section(
       }
     }
   }
+  const double gam0 = (p0[0] + p0[1]) + (p0[2] + p0[3]);
   auto row = [&](int r) -> double { return r < 64 ? bcast(gam0, r) : bcast(gam1, r - 64); };
   const double r_nb = row(nb), r_nb1 = row(nb + 1);  // both read unconditionally
   const double glev = mode == VPM_SHED_BOTH ? r_nb : 0.0;
