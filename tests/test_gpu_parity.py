@@ -50,6 +50,42 @@ def test_one_step_velocities_realtime_pair(ctx, prec):
     _compare_one_step(ctx, W.realtime(K=4, H=1), prec)
 
 
+# Wake counts whose step target count NT = n + 2 N_b + 3 leaves a last pass-A
+# chunk (NT mod 256) of every kind: 1..5 targets (too few lanes per part for
+# the pads below the wake at N_b = 1: the tail path), 41 and 63 (one target
+# per lane over several source parts), 64, 65, 128 and 191 (2..4 targets per
+# lane), 255, and none (NT a multiple of 256); three steps move NT by the two
+# vortices shed per step, so the spread plan changes between steps. On the
+# streamed path (forced) the same counts give last rounds of one to eight
+# waves of targets over 16 .. 2 source parts, and none beyond 512 targets.
+@pytest.mark.parametrize("path", [V.PATH_AUTO, V.PATH_STREAM])
+@pytest.mark.parametrize("nb", [1, 32])
+@pytest.mark.parametrize("prec", [V.FP32C, V.FP64])
+def test_spread_last_chunk_every_remainder(ctx, path, nb, prec):
+    n_surf = 2 * nb + 3
+    rng = np.random.default_rng(17)
+    for r in (1, 2, 3, 5, 41, 63, 64, 65, 128, 191, 255, 256):
+        n = 256 + r - n_surf if r + 256 - n_surf < 512 else r - n_surf
+        wl = W.workload_from_state("spread nb=%d r=%d" % (nb, r), W.make_params(nb),
+                                   W.random_field(rng, n), K=2, H=3,
+                                   eps=W.f32(np.full((2, 3), 0.05)))
+        ctx.set_path(path)
+        try:
+            g = V.run_workload(ctx, wl, prec, final_wake=True, vel_last=True, gamma_s=True)
+        finally:
+            ctx.set_path(V.PATH_AUTO)
+        o = run_oracle(wl, final_wake=True, vel_last=True, gamma_s=True)
+        tol = TOL[prec]
+        for k in range(wl.K):
+            e = rel_l2(vel_segment(g, k), vel_segment(o, k))
+            assert e <= tol, describe(wl.name + " velocity k=%d" % k, err=e)
+        e = rel_l2(g["gamma_s"], o["gamma_s"])
+        assert e <= tol, describe(wl.name + " gamma_s", err=e)
+        assert np.array_equal(g["n_final"], o["n_final"])
+        # both rollouts start from the same field: the same bits
+        assert np.array_equal(vel_segment(g, 0), vel_segment(g, 1))
+
+
 def test_empty_initial_wake(ctx):
     wl = W.workload_from_state("empty", W.make_params(16), (np.zeros(0), np.zeros(0), np.zeros(0)),
                                K=3, H=5, eps=W.f32(np.full((3, 5), 0.1)))
