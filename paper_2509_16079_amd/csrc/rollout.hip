@@ -129,9 +129,26 @@ template <typename R> struct Shared {
 };
 
 __device__ inline float rsq(float d) { return __builtin_amdgcn_rsqf(d); }
-__device__ inline double rsq(double d) { return 1.0 / sqrt(d); }
 __device__ inline float rcp(float d) { return __builtin_amdgcn_rcpf(d); }
-__device__ inline double rcp(double d) { return 1.0 / d; }
+// FP64: the hardware estimates (v_rsq_f64, v_rcp_f64) refined by two
+// Newton-Raphson steps each, which square the relative error twice (from
+// below 2^-22 to the last bits of binary64): y <- y + (y/2)(1 - d y^2) for
+// 1/sqrt(d), y <- y + y (1 - d y) for 1/d. Arguments here are positive,
+// finite and normal (r^4 + r_c^4, r^2 plus the smallest normal). About half
+// the instructions of the correctly rounded 1.0 / sqrt(d) and 1.0 / d; the
+// results differ from those by a few ulp.
+__device__ inline double rsq(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  double e = fma(-d * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-d * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ inline double rcp(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = fma(y, fma(-d, y, 1.0), y);
+  return fma(y, fma(-d, y, 1.0), y);
+}
 __device__ inline float tiny(float) { return 1.17549435e-38f; }
 __device__ inline double tiny(double) { return 2.2250738585072014e-308; }
 

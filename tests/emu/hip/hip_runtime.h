@@ -154,6 +154,8 @@ inline double __longlong_as_double(long long v) { double r; memcpy(&r, &v, 8); r
 #define __builtin_amdgcn_s_getreg(r) ((unsigned)(threadIdx.x >> 6) << 4)
 #define __builtin_amdgcn_rsqf(x) (1.0f / std::sqrt((float)(x)))
 #define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
+#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt((double)(x)))
+#define __builtin_amdgcn_rcp(x) (1.0 / (double)(x))
 inline unsigned long long wall_clock64() { return 0; }
 template <class T> inline T atomicAdd(T *p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 

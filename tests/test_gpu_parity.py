@@ -45,6 +45,21 @@ def test_one_step_velocities_uneven_random_fields(ctx, prec):
     _compare_one_step(ctx, wl, prec)
 
 
+def test_fp64_one_step_at_binary64_accuracy(ctx):
+    # the FP64 pair's 1/sqrt and 1/r^2 are hardware estimates refined by
+    # Newton-Raphson steps: one step of every target stays within a few
+    # hundred ulp of the oracle over sums of up to 1500 terms (the bar
+    # elsewhere is 1e-10)
+    wl = W.uneven_batch(K=12, H=1, n_min=1, n_max=1500)
+    g = V.run_workload(ctx, wl, V.FP64, final_wake=True, vel_last=True, gamma_s=True)
+    o = run_oracle(wl, final_wake=True, vel_last=True, gamma_s=True)
+    for k in range(wl.K):
+        e = rel_l2(vel_segment(g, k), vel_segment(o, k))
+        assert e <= 1e-13, describe("FP64 one-step velocity k=%d" % k, err=e)
+    e = rel_l2(g["gamma_s"], o["gamma_s"])
+    assert e <= 1e-13, describe("FP64 one-step gamma_s", err=e)
+
+
 @pytest.mark.parametrize("prec", [V.FP32C, V.FP64])
 def test_one_step_velocities_realtime_pair(ctx, prec):
     _compare_one_step(ctx, W.realtime(K=4, H=1), prec)
