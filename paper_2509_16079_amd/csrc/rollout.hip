@@ -23,7 +23,8 @@
 //  - rollout_lds_kernel (4 waves): the wake is resident in LDS for the whole
 //    horizon. Sources are split into 4 contiguous quarters (one per wave);
 //    each lane keeps T targets in registers; the quarters are added in FP64
-//    in fixed order.
+//    in fixed order. A step's last, partly filled chunk is spread over all
+//    lanes, each with its targets against one of P equal source parts.
 //  - rollout_stream_kernel (NW waves, persistent): the wake lives in a
 //    per-workgroup slot of a global workspace; 1024-source tiles are staged
 //    cooperatively through LDS and every wave walks all of them for its own
